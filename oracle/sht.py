@@ -1,0 +1,176 @@
+"""Spherical harmonic transforms on HEALPix RING maps (oracle, FP64).
+
+ORACLE -- test infrastructure only; see oracle/__init__.py.
+
+Analysis (map2alm) is the discrete sum of Eq. (1) / Eq. (26),
+    a_lm = sum_p w_p f_p conj(Y_lm)(p),   w_p = 4 pi / Npix (equal weights),
+and synthesis (alm2map) is Eq. (2) / Eq. (24),
+    f_p = sum_{l, -l<=m<=l} a_lm Y_lm(p),   a_{l,-m} = (-1)^m conj(a_lm),
+both evaluated separably (Eq. (12)-(14)): a Fourier sum in longitude on every
+ring, then the Legendre sum over rings (analysis) or over l (synthesis).
+Only m >= 0 is stored (m-major index, see geometry.alm_index); Im(a_l0) is
+ignored on input and 0 on output.  Rings are summed one by one, with no
+north/south parity fold.
+"""
+import numpy as np
+
+from . import geometry
+from .legendre import legendre_analysis, legendre_synthesis
+
+
+def _ring_phase(g, r, mvals, sign):
+    """exp(sign * i * m * phi0_r) with m*phi0 reduced mod 2 pi in integers."""
+    num, den = int(g["phi0_num"][r]), int(g["phi0_den"][r])
+    red = (mvals * num) % (2 * den)
+    return np.exp(sign * 1j * np.pi * red / den)
+
+
+def ring_weights_equal(nside):
+    R = geometry.nrings(nside)
+    return np.full(R, 4.0 * np.pi / geometry.npix(nside))
+
+
+def ring_fourier_forward(maps, nside, lmax, ring_weights=None):
+    """F[r, m, b] = w_r * sum_j f[b, s_r + j] * exp(-i m phi_{r,j}).
+
+    The sum over a ring is evaluated with numpy's FP64 FFT: for phi_{r,j} =
+    phi0_r + 2 pi j / n_r it equals exp(-i m phi0_r) * DFT_n(f)[m mod n].
+    """
+    g = geometry.ring_geometry(nside)
+    maps = np.asarray(maps, dtype=np.float64)
+    B = maps.shape[0]
+    R = len(g["n"])
+    w = ring_weights_equal(nside) if ring_weights is None else ring_weights
+    mvals = np.arange(lmax + 1)
+    F = np.empty((R, lmax + 1, B), dtype=np.complex128)
+    for r in range(R):
+        s, n = int(g["start"][r]), int(g["n"][r])
+        X = np.fft.fft(maps[:, s:s + n], axis=1)  # [B, n]
+        ph = _ring_phase(g, r, mvals, -1.0)
+        F[r] = (w[r] * X[:, mvals % n] * ph[None, :]).T
+    return F
+
+
+def ring_fourier_inverse(G, nside, lmax):
+    """maps[b, s_r + j] = sum_{m=-lmax}^{lmax} G[r, |m|, b]' exp(i m phi_{r,j})
+
+    where G' for negative m is conj(G) (real field) and the m = 0 term uses
+    Re(G).  The frequencies are folded onto k = m mod n_r and summed with a
+    length-n_r inverse DFT.
+    """
+    g = geometry.ring_geometry(nside)
+    R, M, B = G.shape
+    mvals = np.arange(M)
+    out = np.empty((B, geometry.npix(nside)))
+    for r in range(R):
+        s, n = int(g["start"][r]), int(g["n"][r])
+        c = G[r] * _ring_phase(g, r, mvals, +1.0)[:, None]  # [M, B]
+        rows = -(-M // n)
+        pos = np.zeros((rows * n, B), dtype=np.complex128)
+        pos[:M] = c
+        pos[0] = c[0].real
+        neg = np.zeros((rows * n, B), dtype=np.complex128)
+        neg[1:M] = np.conj(c[1:])
+        Cpos = pos.reshape(rows, n, B).sum(axis=0)       # k = m mod n
+        Cneg = neg.reshape(rows, n, B).sum(axis=0)       # indexed by m mod n
+        C = Cpos + Cneg[(-np.arange(n)) % n]              # k = -m mod n
+        f = np.fft.ifft(C, axis=0) * n
+        out[:, s:s + n] = f.real.T
+    return out
+
+
+def map2alm(maps, lmax, nside=None, ring_weights=None, nthreads=None):
+    """Forward SHT of real RING maps [B, Npix] -> complex alm [B, nalm]."""
+    maps = np.atleast_2d(np.asarray(maps, dtype=np.float64))
+    if nside is None:
+        nside = int(round(np.sqrt(maps.shape[1] / 12)))
+    g = geometry.ring_geometry(nside)
+    F = ring_fourier_forward(maps, nside, lmax, ring_weights)
+    return legendre_analysis(lmax, g["z"], g["sth"], F, nthreads)
+
+
+def alm2map(alm, nside, lmax, nthreads=None):
+    """Inverse SHT of complex alm [B, nalm] -> real RING maps [B, Npix]."""
+    alm = np.atleast_2d(np.asarray(alm, dtype=np.complex128)).copy()
+    alm[:, :lmax + 1] = alm[:, :lmax + 1].real  # m = 0 block: Im ignored
+    g = geometry.ring_geometry(nside)
+    G = legendre_synthesis(lmax, g["z"], g["sth"], alm, nthreads)
+    return ring_fourier_inverse(G, nside, lmax)
+
+
+def _m_of_index(lmax):
+    m = np.empty(geometry.nalm(lmax), dtype=np.int64)
+    for mm in range(lmax + 1):
+        a = geometry.alm_index(mm, mm, lmax)
+        m[a:a + lmax + 1 - mm] = mm
+    return m
+
+
+def _l_of_index(lmax):
+    l = np.empty(geometry.nalm(lmax), dtype=np.int64)
+    for mm in range(lmax + 1):
+        a = geometry.alm_index(mm, mm, lmax)
+        l[a:a + lmax + 1 - mm] = np.arange(mm, lmax + 1)
+    return l
+
+
+def map2alm_backward(grad_alm, nside, lmax, nthreads=None):
+    """Gradient w.r.t. the map of a real loss, given dL/d(alm).
+
+    Complex gradients follow PyTorch (dL/dRe + i dL/dIm).  With equal
+    weights w = 4 pi/Npix the adjoint of map2alm (the adjoint SHT "W Y",
+    Sec. III-F) on the m >= 0 storage is w * alm2map(G') with
+    G'_l0 = Re G_l0 and G'_lm = G_lm / 2 for m > 0.
+    """
+    G = np.atleast_2d(np.asarray(grad_alm, dtype=np.complex128)).copy()
+    m = _m_of_index(lmax)
+    G[:, m > 0] *= 0.5
+    G[:, m == 0] = G[:, m == 0].real
+    return alm2map(G, nside, lmax, nthreads) * (4.0 * np.pi / geometry.npix(nside))
+
+
+def alm2map_backward(grad_map, lmax, nside=None, nthreads=None):
+    """Gradient w.r.t. alm of a real loss, given dL/d(map).
+
+    The adjoint iSHT "Y^dagger" (Sec. III-F) on the m >= 0 storage is the
+    unit-weight analysis sum, doubled for m > 0 (each stored a_lm also stands
+    for a_{l,-m}); the m = 0 gradient is real.
+    """
+    g = np.atleast_2d(np.asarray(grad_map, dtype=np.float64))
+    if nside is None:
+        nside = int(round(np.sqrt(g.shape[1] / 12)))
+    ones = np.ones(geometry.nrings(nside))
+    out = map2alm(g, lmax, nside, ring_weights=ones, nthreads=nthreads)
+    m = _m_of_index(lmax)
+    out[:, m > 0] *= 2.0
+    out[:, m == 0] = out[:, m == 0].real
+    return out
+
+
+def jacobi_map2alm(maps, lmax, nside, niter=3, nthreads=None):
+    """Iterative refinement of Eq. (4): a <- a + A(f - S a), niter times.
+
+    Returns the list [a^0, a^1, ..., a^niter] (niter+1 forward and niter
+    inverse transforms).
+    """
+    maps = np.atleast_2d(np.asarray(maps, dtype=np.float64))
+    a = map2alm(maps, lmax, nside, nthreads=nthreads)
+    out = [a]
+    for _ in range(niter):
+        r = maps - alm2map(a, nside, lmax, nthreads)
+        a = a + map2alm(r, lmax, nside, nthreads=nthreads)
+        out.append(a)
+    return out
+
+
+def spectral_loss(alm, lmax):
+    """L = sum_l w_l sum_{stored m>=0} |a_lm|^2 with w_l = 1/(l+1)."""
+    l = _l_of_index(lmax)
+    w = 1.0 / (l + 1.0)
+    return float(np.sum(w[None, :] * np.abs(alm) ** 2))
+
+
+def spectral_loss_grad(alm, lmax):
+    """dL/d(alm) in the PyTorch complex convention: 2 w_l a_lm."""
+    l = _l_of_index(lmax)
+    return 2.0 * (1.0 / (l + 1.0))[None, :] * alm
