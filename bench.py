@@ -1,0 +1,178 @@
+"""Throughput of the HEALPix SHT hot path on one MI355X.
+
+One step = forward (map2alm) + inverse (alm2map) transform of a batch of B
+maps resident in HBM.  Default workload: Nside=1024 (12,582,912 pixels),
+lmax=2047, B=16 FP32 channels of band-limited Gaussian random fields with
+C_l = (l+10)^-2.
+
+Prints one JSON line: maps/s, per-step p50/p99 latency, the roofline of the
+dominant kernel (timed with HIP events recorded on the transform's stream
+inside the timed region) and the FP64 CPU oracle's rate on a bounded sample.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {  # MI355X published peaks
+    "hbm_GBs": 8000.0,
+    "fp32_vector_TFs": 157.3,
+    "fp64_vector_TFs": 78.6,
+    "fp32_mfma_TFs": 157.3,
+}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--nside", type=int, default=1024)
+    ap.add_argument("--lmax", type=int, default=None)
+    ap.add_argument("--batch", type=int, default=16)
+    ap.add_argument("--dtype", default="f32", choices=["f32", "f64", "bf16"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-nside", type=int, default=None)
+    return ap.parse_args()
+
+
+def triples(nside, lmax):
+    return (lmax + 1) * (lmax + 2) // 2 * (2 * nside)
+
+
+def cpu_baseline(nside, lmax, seed):
+    """The FP64 oracle, as it stands, on one map of the same workload: forward
+    + inverse, all host threads."""
+    from oracle import _clib, sht
+    from paper_2510_01785_amd import synth
+    alm = synth.gaussian_alm(seed, 1, lmax, "lp10")
+    f = synth.white_map(seed, 1, 12 * nside * nside)
+    _clib.build()
+    t0 = time.perf_counter()
+    a = sht.map2alm(f, lmax, nside)
+    sht.alm2map(alm, nside, lmax)
+    dt = time.perf_counter() - t0
+    del a
+    return dict(value=1.0 / dt, unit="maps/s", cores=_clib.threads(), kind="oracle",
+                sample="1 channel of the workload (nside=%d, lmax=%d), forward + inverse, %.1f s"
+                % (nside, lmax, dt))
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the transform is not sharded across GPUs "
+              "(see DESIGN.md for how it would shard); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_2510_01785_amd as shtx
+    from paper_2510_01785_amd import _lib, synth
+
+    nside, B = args.nside, args.batch
+    lmax = args.lmax if args.lmax is not None else 2 * nside - 1
+    dt = {"f32": torch.float32, "f64": torch.float64, "bf16": torch.bfloat16}[args.dtype]
+    ct = torch.complex128 if args.dtype == "f64" else torch.complex64
+    dev = torch.device("cuda:0")
+    seed = 17853
+    print("[bench] setup nside=%d lmax=%d B=%d %s" % (nside, lmax, B, args.dtype), flush=True)
+    alm0 = torch.tensor(synth.gaussian_alm(seed, B, lmax, "lp10"), dtype=ct, device=dev)
+    shtx.get_tables(nside, lmax, dev)
+    map_dtype = torch.float64 if args.dtype == "f64" else torch.float32
+    maps = shtx.alm2map_raw(alm0.to(torch.complex128 if map_dtype == torch.float64 else torch.complex64),
+                            nside, lmax).to(dt)
+    torch.cuda.synchronize()
+    L = _lib.lib()
+
+    def step():
+        a = shtx.map2alm_raw(maps, lmax)
+        if args.dtype == "bf16":
+            return a
+        return shtx.alm2map_raw(a, nside, lmax)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    print("[bench] warmup done", flush=True)
+    stream = torch.cuda.current_stream(dev)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    L.shtx_profile_reset()
+    L.shtx_profile_enable(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        evs[i][0].record(stream)
+        step()
+        evs[i][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    L.shtx_profile_enable(0)
+    prof = _lib.profile_read()
+    lat = np.array([a.elapsed_time(b) for a, b in evs])
+    print("[bench] timed %d steps in %.3f s" % (args.steps, wall), flush=True)
+
+    value = B * args.steps / wall
+    ms_per_step = 1000.0 * wall / args.steps
+    # roofline of the dominant stage
+    stages = {k: dict(ms_per_call=v[0] / max(v[1], 1), calls=v[1]) for k, v in prof.items() if v[1]}
+    dom = max(stages, key=lambda k: stages[k]["ms_per_call"])
+    tr = triples(nside, lmax)
+    csize = 16 if args.dtype == "f64" else 8
+    esize = {"f32": 4, "f64": 8, "bf16": 2}[args.dtype]
+    npix = 12 * nside * nside
+    spec_bytes = 2 * (lmax + 1) * 2 * nside * B * csize
+    alm_bytes = (lmax + 1) * (lmax + 2) // 2 * B * csize
+    work = {
+        # algorithmic work per call of each stage
+        "legendre_fwd": ("alu", 4.0 * tr * B, "TFLOP/s"),
+        "legendre_inv": ("alu", 4.0 * tr * B, "TFLOP/s"),
+        "ring_fft_fwd": ("hbm", float(npix * B * esize + spec_bytes), "GB/s"),
+        "ring_fft_inv": ("hbm", float(npix * B * esize + spec_bytes), "GB/s"),
+        "alm_out": ("hbm", 2.0 * alm_bytes, "GB/s"),
+        "alm_in": ("hbm", 2.0 * alm_bytes, "GB/s"),
+    }
+    bound, amount, unit = work[dom]
+    sec = stages[dom]["ms_per_call"] / 1000.0
+    if unit == "TFLOP/s":
+        achieved = amount / sec / 1e12
+        peak = PEAK["fp64_vector_TFs"] if args.dtype == "f64" else PEAK["fp32_vector_TFs"]
+    else:
+        achieved = amount / sec / 1e9
+        peak = PEAK["hbm_GBs"]
+    roof = dict(kernel=dom, bound=bound, achieved=round(achieved, 3), peak=peak, unit=unit,
+                frac=round(achieved / peak, 4), traffic=None)
+    out = {
+        "metric": "SHT fwd+inv maps/s at Nside=1024 lmax=2047 B=16; % roofline; p50/p99 latency",
+        "value": round(value, 3),
+        "unit": "maps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "p50_ms": round(float(np.percentile(lat, 50)), 4),
+        "p99_ms": round(float(np.percentile(lat, 99)), 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.dtype,
+        "data": "synthetic",
+        "config": {"workload": "healpix_sht_fwd_inv", "nside": nside, "lmax": lmax, "batch": B,
+                   "fields": "gaussian C_l=(l+10)^-2"},
+        "stages_ms_per_call": {k: round(v["ms_per_call"], 4) for k, v in stages.items()},
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle)", flush=True)
+        cs = args.cpu_sample_nside or nside
+        out["cpu_baseline"] = cpu_baseline(cs, 2 * cs - 1, seed)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

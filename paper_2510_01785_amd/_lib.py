@@ -1,0 +1,79 @@
+"""ctypes binding of libshtx.so (argument marshalling only)."""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libshtx.so")
+
+F64, F32, BF16 = 0, 1, 2
+OK, ERR_ARG, ERR_UNSUPPORTED, ERR_WORKSPACE, ERR_HIP, ERR_TABLES = range(6)
+
+EXPORTS = ("shtx_version", "shtx_status_string", "shtx_tables_bytes", "shtx_tables_build",
+           "shtx_tables_release", "shtx_workspace_bytes", "shtx_map2alm", "shtx_alm2map",
+           "shtx_map2alm_backward", "shtx_alm2map_backward", "shtx_profile_enable",
+           "shtx_profile_reset", "shtx_profile_read", "shtx_stage_name")
+STAGES = ("ring_fft_fwd", "legendre_fwd", "alm_out", "alm_in", "legendre_inv", "ring_fft_inv")
+
+_lib = None
+
+
+class ShtxError(RuntimeError):
+    def __init__(self, fn, status):
+        self.status = status
+        msg = lib().shtx_status_string(status).decode()
+        super().__init__("%s failed: %s (status %d)" % (fn, msg, status))
+
+
+def lib():
+    """Load libshtx.so; raises if it has not been built (no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libshtx.so not built: run python -m paper_2510_01785_amd.build "
+                          "(or __graft_entry__.build())")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, sz, i = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int
+    L.shtx_version.argtypes = []
+    L.shtx_version.restype = i
+    L.shtx_status_string.argtypes = [i]
+    L.shtx_status_string.restype = ctypes.c_char_p
+    L.shtx_tables_bytes.argtypes = [i, i]
+    L.shtx_tables_bytes.restype = sz
+    L.shtx_tables_build.argtypes = [i, i, vp, sz, vp]
+    L.shtx_tables_build.restype = i
+    L.shtx_tables_release.argtypes = [vp]
+    L.shtx_tables_release.restype = i
+    L.shtx_workspace_bytes.argtypes = [i, i, i, i]
+    L.shtx_workspace_bytes.restype = sz
+    for name in ("shtx_map2alm", "shtx_alm2map", "shtx_map2alm_backward", "shtx_alm2map_backward"):
+        f = getattr(L, name)
+        f.argtypes = [i, i, i, i, vp, vp, vp, vp, sz, vp]
+        f.restype = i
+    L.shtx_profile_enable.argtypes = [i]
+    L.shtx_profile_enable.restype = i
+    L.shtx_profile_reset.argtypes = []
+    L.shtx_profile_reset.restype = i
+    L.shtx_profile_read.argtypes = [i, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_longlong)]
+    L.shtx_profile_read.restype = i
+    L.shtx_stage_name.argtypes = [i]
+    L.shtx_stage_name.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def profile_read():
+    """{stage name: (total GPU ms, launches)} since the last reset."""
+    L = lib()
+    out = {}
+    for s, name in enumerate(STAGES):
+        ms = ctypes.c_double()
+        n = ctypes.c_longlong()
+        check("shtx_profile_read", L.shtx_profile_read(s, ctypes.byref(ms), ctypes.byref(n)))
+        out[name] = (ms.value, n.value)
+    return out
+
+
+def check(fn, status):
+    if status != OK:
+        raise ShtxError(fn, status)

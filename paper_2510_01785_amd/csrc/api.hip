@@ -1,0 +1,312 @@
+// C ABI of libshtx.so (declared in include/shtx.h): host-side validation,
+// table registry, workspace carving and kernel dispatch.
+#include <mutex>
+#include <unordered_map>
+#include <utility>
+#include <vector>
+
+#include "../../include/shtx.h"
+#include "common.h"
+
+namespace shtx {
+
+hipError_t launch_tables_build(int nside, int lmax, void *base, hipStream_t st);
+template <typename TIn, typename T>
+hipError_t launch_ring_fft_fwd(const Tables &, int, const TIn *, const double *, double, cplx<T> *, cplx<T> *,
+                               hipStream_t);
+template <typename TOut, typename T>
+hipError_t launch_ring_fft_inv(const Tables &, int, const cplx<T> *, const cplx<T> *, TOut *, hipStream_t);
+template <typename T>
+hipError_t launch_legendre_fwd_valu(const Tables &, int, const cplx<T> *, const cplx<T> *, cplx<T> *, hipStream_t);
+template <typename T>
+hipError_t launch_legendre_inv_valu(const Tables &, int, const cplx<T> *, cplx<T> *, cplx<T> *, hipStream_t);
+template <typename T, typename TO>
+hipError_t launch_alm_out(int, int, const cplx<T> *, cplx<TO> *, double, double, hipStream_t);
+template <typename T, typename TI>
+hipError_t launch_alm_in(int, int, const cplx<TI> *, const double *, cplx<T> *, double, double, double,
+                         hipStream_t);
+
+namespace {
+
+// ------------------------------------------------------------ stage timing
+enum Stage { kStFftFwd = 0, kStLegFwd, kStAlmOut, kStAlmIn, kStLegInv, kStFftInv, kNumStages };
+const char *kStageNames[kNumStages] = {"ring_fft_fwd", "legendre_fwd", "alm_out",
+                                       "alm_in",       "legendre_inv", "ring_fft_inv"};
+
+struct Profiler {
+  std::mutex mu;
+  bool on = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[kNumStages];
+  double ms[kNumStages] = {};
+  long long n[kNumStages] = {};
+} g_prof;
+
+// Records start/stop events around one stage when profiling is on.
+struct StageTimer {
+  int stage;
+  hipStream_t st;
+  hipEvent_t a = nullptr, b = nullptr;
+  StageTimer(int s, hipStream_t stream) : stage(s), st(stream) {
+    if (!g_prof.on) return;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+      a = b = nullptr;
+      return;
+    }
+    hipEventRecord(a, st);
+  }
+  ~StageTimer() {
+    if (!a) return;
+    hipEventRecord(b, st);
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    g_prof.ev[stage].emplace_back(a, b);
+  }
+};
+
+void profile_collect() {
+  for (int s = 0; s < kNumStages; ++s) {
+    for (auto &e : g_prof.ev[s]) {
+      float t = 0.f;
+      hipEventSynchronize(e.second);
+      if (hipEventElapsedTime(&t, e.first, e.second) == hipSuccess) {
+        g_prof.ms[s] += t;
+        g_prof.n[s] += 1;
+      }
+      hipEventDestroy(e.first);
+      hipEventDestroy(e.second);
+    }
+    g_prof.ev[s].clear();
+  }
+}
+
+std::mutex g_mu;
+std::unordered_map<const void *, std::pair<int, int>> g_tables;
+
+bool valid_geom(int nside, int lmax) {
+  if (nside < 1 || (nside & (nside - 1)) != 0) return false;
+  if (lmax < 0 || lmax > 8191) return false;
+  return true;
+}
+
+int check_common(int nside, int lmax, int batch, int dtype, const void *in, const void *out, const void *tables,
+                 const void *work, size_t work_bytes) {
+  if (!valid_geom(nside, lmax) || batch < 1) return SHTX_ERR_ARG;
+  if (dtype != SHTX_F64 && dtype != SHTX_F32 && dtype != SHTX_BF16) return SHTX_ERR_ARG;
+  if (!in || !out || !tables || !work) return SHTX_ERR_ARG;
+  if (nside > kMaxNside) return SHTX_ERR_UNSUPPORTED;
+  if (reinterpret_cast<uintptr_t>(work) % 256 != 0) return SHTX_ERR_ARG;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_tables.find(tables);
+    if (it == g_tables.end() || it->second.first != nside || it->second.second != lmax) return SHTX_ERR_TABLES;
+  }
+  if (work_bytes < shtx_workspace_bytes(nside, lmax, batch, dtype)) return SHTX_ERR_WORKSPACE;
+  return SHTX_OK;
+}
+
+template <typename T> struct Work {
+  cplx<T> *specA, *specB, *almt;
+};
+
+template <typename T> Work<T> carve(void *work, int nside, int lmax, int batch) {
+  const size_t cs = sizeof(cplx<T>);
+  const size_t spec = (size_t)(lmax + 1) * (size_t)(2 * nside) * (size_t)batch * cs;
+  char *b = static_cast<char *>(work);
+  Work<T> w;
+  w.specA = reinterpret_cast<cplx<T> *>(b);
+  w.specB = reinterpret_cast<cplx<T> *>(b + align_up(spec, 256));
+  w.almt = reinterpret_cast<cplx<T> *>(b + 2 * align_up(spec, 256));
+  return w;
+}
+
+int status_of(hipError_t e) { return e == hipSuccess ? SHTX_OK : SHTX_ERR_HIP; }
+
+// analysis chain: ring FFT -> Legendre -> caller layout with factors
+template <typename TIn, typename T>
+int run_analysis(const Tables &tb, int B, const TIn *map, cplx<T> *alm, const double *wtab, double wscale,
+                 double f0, double fm, void *work, hipStream_t st) {
+  Work<T> w = carve<T>(work, tb.nside, tb.lmax, B);
+  hipError_t e;
+  {
+    StageTimer t(kStFftFwd, st);
+    e = launch_ring_fft_fwd<TIn, T>(tb, B, map, wtab, wscale, w.specA, w.specB, st);
+  }
+  if (e != hipSuccess) return SHTX_ERR_HIP;
+  {
+    StageTimer t(kStLegFwd, st);
+    e = launch_legendre_fwd_valu<T>(tb, B, w.specA, w.specB, w.almt, st);
+  }
+  if (e != hipSuccess) return SHTX_ERR_HIP;
+  StageTimer t(kStAlmOut, st);
+  return status_of(launch_alm_out<T, T>(tb.lmax, B, w.almt, alm, f0, fm, st));
+}
+
+// synthesis chain: caller layout with factors -> Legendre -> ring FFT
+template <typename TOut, typename T>
+int run_synthesis(const Tables &tb, int B, const cplx<T> *alm, TOut *map, double s, double f0, double fm, void *work,
+                  hipStream_t st) {
+  Work<T> w = carve<T>(work, tb.nside, tb.lmax, B);
+  hipError_t e;
+  {
+    StageTimer t(kStAlmIn, st);
+    e = launch_alm_in<T, T>(tb.lmax, B, alm, tb.coefC, w.almt, s, f0, fm, st);
+  }
+  if (e != hipSuccess) return SHTX_ERR_HIP;
+  {
+    StageTimer t(kStLegInv, st);
+    e = launch_legendre_inv_valu<T>(tb, B, w.almt, w.specA, w.specB, st);
+  }
+  if (e != hipSuccess) return SHTX_ERR_HIP;
+  StageTimer t(kStFftInv, st);
+  return status_of(launch_ring_fft_inv<TOut, T>(tb, B, w.specA, w.specB, map, st));
+}
+
+}  // namespace
+}  // namespace shtx
+
+using namespace shtx;
+
+extern "C" {
+
+int shtx_version(void) { return 100; }
+
+int shtx_profile_enable(int on) {
+  std::lock_guard<std::mutex> lk(g_prof.mu);
+  g_prof.on = on != 0;
+  return SHTX_OK;
+}
+
+int shtx_profile_reset(void) {
+  std::lock_guard<std::mutex> lk(g_prof.mu);
+  profile_collect();
+  for (int s = 0; s < kNumStages; ++s) {
+    g_prof.ms[s] = 0.0;
+    g_prof.n[s] = 0;
+  }
+  return SHTX_OK;
+}
+
+int shtx_profile_read(int stage, double *total_ms, long long *launches) {
+  if (stage < 0 || stage >= kNumStages || !total_ms || !launches) return SHTX_ERR_ARG;
+  std::lock_guard<std::mutex> lk(g_prof.mu);
+  profile_collect();
+  *total_ms = g_prof.ms[stage];
+  *launches = g_prof.n[stage];
+  return SHTX_OK;
+}
+
+const char *shtx_stage_name(int stage) {
+  if (stage < 0 || stage >= kNumStages) return "unknown";
+  return kStageNames[stage];
+}
+
+const char *shtx_status_string(int status) {
+  switch (status) {
+    case SHTX_OK: return "ok";
+    case SHTX_ERR_ARG: return "invalid argument";
+    case SHTX_ERR_UNSUPPORTED: return "unsupported configuration";
+    case SHTX_ERR_WORKSPACE: return "workspace too small";
+    case SHTX_ERR_HIP: return "HIP runtime error";
+    case SHTX_ERR_TABLES: return "tables not built for this (nside, lmax)";
+    default: return "unknown status";
+  }
+}
+
+size_t shtx_tables_bytes(int nside, int lmax) {
+  if (!valid_geom(nside, lmax) || nside > kMaxNside) return 0;
+  return table_offsets(nside, lmax).total;
+}
+
+int shtx_tables_build(int nside, int lmax, void *tables, size_t tables_bytes, void *stream) {
+  if (!valid_geom(nside, lmax) || !tables) return SHTX_ERR_ARG;
+  if (nside > kMaxNside) return SHTX_ERR_UNSUPPORTED;
+  if (reinterpret_cast<uintptr_t>(tables) % 256 != 0) return SHTX_ERR_ARG;
+  if (tables_bytes < shtx_tables_bytes(nside, lmax)) return SHTX_ERR_WORKSPACE;
+  const hipError_t e = launch_tables_build(nside, lmax, tables, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return SHTX_ERR_HIP;
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_tables[tables] = std::make_pair(nside, lmax);
+  return SHTX_OK;
+}
+
+int shtx_tables_release(const void *tables) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  return g_tables.erase(tables) ? SHTX_OK : SHTX_ERR_TABLES;
+}
+
+size_t shtx_workspace_bytes(int nside, int lmax, int batch, int dtype) {
+  if (!valid_geom(nside, lmax) || batch < 1) return 0;
+  if (dtype != SHTX_F64 && dtype != SHTX_F32 && dtype != SHTX_BF16) return 0;
+  const size_t cs = dtype == SHTX_F64 ? 16 : 8;
+  const size_t spec = (size_t)(lmax + 1) * (size_t)(2 * nside) * (size_t)batch * cs;
+  const size_t almt = nalm_of(lmax) * (size_t)batch * cs;
+  return 2 * align_up(spec, 256) + align_up(almt, 256);
+}
+
+int shtx_map2alm(int nside, int lmax, int batch, int dtype, const void *map, void *alm, const void *tables,
+                 void *work, size_t work_bytes, void *stream) {
+  int s = check_common(nside, lmax, batch, dtype, map, alm, tables, work, work_bytes);
+  if (s != SHTX_OK) return s;
+  const Tables tb = tables_view(tables, nside, lmax);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  switch (dtype) {
+    case SHTX_F64:
+      return run_analysis<double, double>(tb, batch, static_cast<const double *>(map), static_cast<double2 *>(alm),
+                                          tb.rp_w, 1.0, 1.0, 1.0, work, st);
+    case SHTX_F32:
+      return run_analysis<float, float>(tb, batch, static_cast<const float *>(map), static_cast<float2 *>(alm),
+                                        tb.rp_w, 1.0, 1.0, 1.0, work, st);
+    default:
+      return run_analysis<bf16_t, float>(tb, batch, static_cast<const bf16_t *>(map), static_cast<float2 *>(alm),
+                                         tb.rp_w, 1.0, 1.0, 1.0, work, st);
+  }
+}
+
+int shtx_alm2map(int nside, int lmax, int batch, int dtype, const void *alm, void *map, const void *tables,
+                 void *work, size_t work_bytes, void *stream) {
+  int s = check_common(nside, lmax, batch, dtype, alm, map, tables, work, work_bytes);
+  if (s != SHTX_OK) return s;
+  if (dtype == SHTX_BF16) return SHTX_ERR_UNSUPPORTED;
+  const Tables tb = tables_view(tables, nside, lmax);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (dtype == SHTX_F64)
+    return run_synthesis<double, double>(tb, batch, static_cast<const double2 *>(alm), static_cast<double *>(map),
+                                         1.0, 1.0, 1.0, work, st);
+  return run_synthesis<float, float>(tb, batch, static_cast<const float2 *>(alm), static_cast<float *>(map), 1.0,
+                                     1.0, 1.0, work, st);
+}
+
+int shtx_map2alm_backward(int nside, int lmax, int batch, int dtype, const void *grad_alm, void *grad_map,
+                          const void *tables, void *work, size_t work_bytes, void *stream) {
+  int s = check_common(nside, lmax, batch, dtype, grad_alm, grad_map, tables, work, work_bytes);
+  if (s != SHTX_OK) return s;
+  const Tables tb = tables_view(tables, nside, lmax);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const double w = 4.0 * M_PI / (double)tb.npix;
+  switch (dtype) {
+    case SHTX_F64:
+      return run_synthesis<double, double>(tb, batch, static_cast<const double2 *>(grad_alm),
+                                           static_cast<double *>(grad_map), w, 1.0, 0.5, work, st);
+    case SHTX_F32:
+      return run_synthesis<float, float>(tb, batch, static_cast<const float2 *>(grad_alm),
+                                         static_cast<float *>(grad_map), w, 1.0, 0.5, work, st);
+    default:
+      return run_synthesis<bf16_t, float>(tb, batch, static_cast<const float2 *>(grad_alm),
+                                          static_cast<bf16_t *>(grad_map), w, 1.0, 0.5, work, st);
+  }
+}
+
+int shtx_alm2map_backward(int nside, int lmax, int batch, int dtype, const void *grad_map, void *grad_alm,
+                          const void *tables, void *work, size_t work_bytes, void *stream) {
+  int s = check_common(nside, lmax, batch, dtype, grad_map, grad_alm, tables, work, work_bytes);
+  if (s != SHTX_OK) return s;
+  if (dtype == SHTX_BF16) return SHTX_ERR_UNSUPPORTED;
+  const Tables tb = tables_view(tables, nside, lmax);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (dtype == SHTX_F64)
+    return run_analysis<double, double>(tb, batch, static_cast<const double *>(grad_map),
+                                        static_cast<double2 *>(grad_alm), nullptr, 1.0, 1.0, 2.0, work, st);
+  return run_analysis<float, float>(tb, batch, static_cast<const float *>(grad_map), static_cast<float2 *>(grad_alm),
+                                    nullptr, 1.0, 1.0, 2.0, work, st);
+}
+
+}  // extern "C"

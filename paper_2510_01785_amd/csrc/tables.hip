@@ -1,0 +1,192 @@
+// Resident tables for one (nside, lmax): ring-pair geometry, recurrence
+// coefficients, Legendre seeds at each ring's first non-negligible l, and the
+// roots of unity of every ring length.  All of it is computed on the device in
+// FP64 by the kernels below; nothing is copied from the host.
+//
+// Legendre normalisation.  The orthonormal lambda_lm of Eq. (8) (with the
+// (-1)^m of Eq. (15)) obeys the three-term recurrence of Eq. (16):
+//   lambda_l = alpha_l z lambda_{l-1} - alpha_l beta_l lambda_{l-2},
+//   alpha_l = sqrt((4l^2-1)/(l^2-m^2)), beta_l = sqrt(((l-1)^2-m^2)/(4(l-1)^2-1)).
+// The kernels run it on mu_l = lambda_l / c_l with c_m = c_{m+1} = 1 and
+// c_l = alpha_l beta_l c_{l-2}, which turns it into
+//   mu_l = A_l z mu_{l-1} - mu_{l-2},   A_l = alpha_l c_{l-1} / c_l,
+// one multiply and one fused multiply-add per step; c_l (0.17 .. 1.13 for
+// l <= 4095) is applied once per coefficient, outside the ring sums.
+#include "common.h"
+
+namespace shtx {
+
+__global__ void k_ring_pairs(int N, int *rp_n, int *rp_sN, int *rp_sS, int *p0n, int *p0d,
+                             double *z_out, double *sth_out, double *w_out) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= 2 * N) return;
+  const int i = p + 1;  // north ring number, 1 .. 2N
+  const long long npix = 12LL * N * N;
+  int n, sN, num, den;
+  double z;
+  if (i < N) {  // north polar cap
+    n = 4 * i;
+    z = 1.0 - (double)((long long)i * i) / (3.0 * (double)N * (double)N);
+    sN = 2 * i * (i - 1);
+    num = 1;
+    den = 4 * i;
+  } else {  // belt, north half (incl. equator)
+    n = 4 * N;
+    z = (double)(4 * N - 2 * i) / (3.0 * (double)N);
+    sN = 2 * N * (N - 1) + 4 * N * (i - N);
+    if (((i - N) & 1) == 0) {
+      num = 1;
+      den = 4 * N;
+    } else {
+      num = 0;
+      den = 1;
+    }
+  }
+  // south partner 4N - i: same length and phi0; RING start by symmetry
+  const int sS = (i == 2 * N) ? sN : (int)(npix - (long long)sN - n);
+  rp_n[p] = n;
+  rp_sN[p] = sN;
+  rp_sS[p] = sS;
+  p0n[p] = num;
+  p0d[p] = den;
+  z_out[p] = z;
+  sth_out[p] = sqrt((1.0 - z) * (1.0 + z));
+  w_out[p] = 4.0 * M_PI / (double)npix;
+}
+
+// One thread per m: c_lm and A_lm for l = m..L (m-major packed index).
+__global__ void k_coefs(int L, double *coefA, double *coefC) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m > L) return;
+  const double dm = m;
+  double c2 = 1.0, c1 = 1.0;  // c_{l-2}, c_{l-1}
+  size_t base = alm_idx(m, m, L);
+  coefC[base] = 1.0;
+  coefA[base] = 0.0;
+  for (int l = m + 1; l <= L; ++l) {
+    const double dl = l;
+    const double alpha = sqrt((4.0 * dl * dl - 1.0) / (dl * dl - dm * dm));
+    double c;
+    if (l == m + 1) {
+      c = 1.0;
+    } else {
+      const double beta = sqrt(((dl - 1.0) * (dl - 1.0) - dm * dm) / (4.0 * (dl - 1.0) * (dl - 1.0) - 1.0));
+      c = alpha * beta * c2;
+    }
+    coefC[base + (l - m)] = c;
+    coefA[base + (l - m)] = alpha * c1 / c;
+    c2 = c1;
+    c1 = c;
+  }
+}
+
+// One thread per ring pair: lambda_mm for m = 0..L as (mantissa, exponent),
+// lambda_mm = -sqrt((2m+1)/(2m)) sin(theta) lambda_{m-1,m-1}, lambda_00 = 1/sqrt(4 pi).
+// Stashed in seed_v[m*Rp + p] = (mantissa, exponent) for k_seeds.
+__global__ void k_lambda_mm(int L, int Rp, const double *sth, double2 *stash) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= Rp) return;
+  const double s = sth[p];
+  double x = 1.0 / sqrt(4.0 * M_PI);
+  int e = 0;
+  stash[p] = make_double2(x, 0.0);
+  for (int m = 1; m <= L; ++m) {
+    x *= -sqrt((2.0 * m + 1.0) / (2.0 * m)) * s;
+    int de;
+    x = frexp(x, &de);
+    e += de;
+    stash[(size_t)m * Rp + p] = make_double2(x, (double)e);
+  }
+}
+
+// One thread per (m, p): walk mu_l from l = m (value x * 2^e, rescaled to keep
+// the mantissas in range) to the first l with |mu_l| >= 2^kSkipExp, align that
+// start down to m + kAlign*j, and store the plain doubles (mu_{ls-1}, mu_ls)
+// there.  Rings that never reach the threshold get ls = L+1.
+__global__ void k_seeds(int L, int Rp, const double *zarr, const double *coefA, int *seed_l,
+                        double2 *seed_v) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  const int m = blockIdx.y;
+  if (p >= Rp) return;
+  const size_t slot = (size_t)m * Rp + p;
+  const double2 st = seed_v[slot];
+  const double z = zarr[p];
+  const double *A = coefA + alm_idx(m, m, L) - m;  // A[l]
+  const int e0 = (int)st.y;
+  // pass 1: find the first l whose value reaches the threshold
+  int lstar = L + 1;
+  {
+    double a = 0.0, b = st.x;  // mu_{l-1}, mu_l mantissas
+    int e = e0;
+    for (int l = m; l <= L; ++l) {
+      if (l > m) {
+        const double nb = A[l] * z * b - a;
+        a = b;
+        b = nb;
+      }
+      if (b != 0.0 && ilogb(b) + e >= kSkipExp) {
+        lstar = l;
+        break;
+      }
+      if (fabs(b) > 0x1p300) {
+        a = ldexp(a, -300);
+        b = ldexp(b, -300);
+        e += 300;
+      }
+    }
+  }
+  if (lstar > L) {
+    seed_l[slot] = L + 1;
+    seed_v[slot] = make_double2(0.0, 0.0);
+    return;
+  }
+  const int ls = m + ((lstar - m) / kAlign) * kAlign;
+  // pass 2: rerun up to ls and convert to plain doubles
+  double a = 0.0, b = st.x;
+  int e = e0;
+  for (int l = m + 1; l <= ls; ++l) {
+    const double nb = A[l] * z * b - a;
+    a = b;
+    b = nb;
+    if (fabs(b) > 0x1p300) {
+      a = ldexp(a, -300);
+      b = ldexp(b, -300);
+      e += 300;
+    }
+  }
+  seed_l[slot] = ls;
+  seed_v[slot] = make_double2(ldexp(a, e), ldexp(b, e));
+}
+
+// Roots exp(-2 pi i k / n) for n = 4i, i = blockIdx.y + 1.
+__global__ void k_roots(int N, double2 *r64, float2 *r32) {
+  const int i = blockIdx.y + 1;
+  const int n = 4 * i;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  double s, c;
+  sincospi((double)k / (2.0 * (double)i), &s, &c);
+  const size_t o = roots_offset(i) + k;
+  r64[o] = make_double2(c, -s);
+  r32[o] = make_float2((float)c, (float)-s);
+}
+
+hipError_t launch_tables_build(int nside, int lmax, void *base, hipStream_t st) {
+  const TableOffsets o = table_offsets(nside, lmax);
+  char *b = static_cast<char *>(base);
+  const int Rp = 2 * nside;
+  auto I = [&](size_t off) { return reinterpret_cast<int *>(b + off); };
+  auto D = [&](size_t off) { return reinterpret_cast<double *>(b + off); };
+  hipLaunchKernelGGL(k_ring_pairs, dim3((Rp + 255) / 256), dim3(256), 0, st, nside, I(o.rp_n), I(o.rp_sN),
+                     I(o.rp_sS), I(o.rp_p0n), I(o.rp_p0d), D(o.rp_z), D(o.rp_sth), D(o.rp_w));
+  hipLaunchKernelGGL(k_coefs, dim3((lmax + 1 + 63) / 64), dim3(64), 0, st, lmax, D(o.coefA), D(o.coefC));
+  double2 *sv = reinterpret_cast<double2 *>(b + o.seed_v);
+  hipLaunchKernelGGL(k_lambda_mm, dim3((Rp + 63) / 64), dim3(64), 0, st, lmax, Rp, D(o.rp_sth), sv);
+  hipLaunchKernelGGL(k_seeds, dim3((Rp + 63) / 64, lmax + 1), dim3(64), 0, st, lmax, Rp, D(o.rp_z),
+                     D(o.coefA), I(o.seed_l), sv);
+  hipLaunchKernelGGL(k_roots, dim3((4 * nside + 255) / 256, nside), dim3(256), 0, st, nside,
+                     reinterpret_cast<double2 *>(b + o.roots64), reinterpret_cast<float2 *>(b + o.roots32));
+  return hipGetLastError();
+}
+
+}  // namespace shtx

@@ -1,0 +1,177 @@
+"""PyTorch-facing transforms over the libshtx C ABI.
+
+PyTorch only provides device memory and the current HIP stream; every step of
+the transforms runs in the library's kernels.  Tables are built once per
+(nside, lmax, device) and kept resident; workspaces come from torch's caching
+allocator per call.
+"""
+import threading
+
+import torch
+
+from . import _lib
+
+_DTYPES = {torch.float64: _lib.F64, torch.float32: _lib.F32, torch.bfloat16: _lib.BF16}
+_ALM_DTYPE = {_lib.F64: torch.complex128, _lib.F32: torch.complex64, _lib.BF16: torch.complex64}
+_ALM_CODE = {torch.complex128: _lib.F64, torch.complex64: _lib.F32}
+
+_tables = {}
+_tables_lock = threading.Lock()
+
+
+def nalm(lmax):
+    return (lmax + 1) * (lmax + 2) // 2
+
+
+def npix(nside):
+    return 12 * nside * nside
+
+
+def nside_of(npix_):
+    n = int(round((npix_ / 12) ** 0.5))
+    if 12 * n * n != npix_:
+        raise ValueError("%d is not a HEALPix pixel count" % npix_)
+    return n
+
+
+def _stream_ptr(device):
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def get_tables(nside, lmax, device):
+    """Resident uint8 table tensor for (nside, lmax) on `device`."""
+    device = torch.device(device)
+    key = (nside, lmax, device.index if device.index is not None else torch.cuda.current_device())
+    with _tables_lock:
+        t = _tables.get(key)
+        if t is not None:
+            return t
+        L = _lib.lib()
+        nb = L.shtx_tables_bytes(nside, lmax)
+        if nb == 0:
+            raise ValueError("invalid (nside, lmax) = (%d, %d)" % (nside, lmax))
+        t = torch.empty(nb, dtype=torch.uint8, device=device)
+        _lib.check("shtx_tables_build",
+                   L.shtx_tables_build(nside, lmax, t.data_ptr(), nb, _stream_ptr(device)))
+        _tables[key] = t
+        return t
+
+
+def clear_tables():
+    with _tables_lock:
+        L = _lib.lib()
+        for t in _tables.values():
+            L.shtx_tables_release(t.data_ptr())
+        _tables.clear()
+
+
+def workspace_bytes(nside, lmax, batch, code):
+    return _lib.lib().shtx_workspace_bytes(nside, lmax, batch, code)
+
+
+def _call(fn, nside, lmax, batch, code, src, dst, device):
+    L = _lib.lib()
+    tab = get_tables(nside, lmax, device)
+    wb = L.shtx_workspace_bytes(nside, lmax, batch, code)
+    work = torch.empty(wb, dtype=torch.uint8, device=device)
+    st = getattr(L, fn)(nside, lmax, batch, code, src.data_ptr(), dst.data_ptr(), tab.data_ptr(),
+                        work.data_ptr(), wb, _stream_ptr(device))
+    _lib.check(fn, st)
+    return dst
+
+
+def _as_batched(x):
+    return (x.unsqueeze(0), True) if x.dim() == 1 else (x, False)
+
+
+def _check_device(x):
+    if not x.is_cuda:
+        raise ValueError("shtx transforms need a tensor on a ROCm device")
+
+
+# ------------------------------------------------------------------ raw ops
+def map2alm_raw(maps, lmax):
+    """maps [B, Npix] (float64/float32/bfloat16, RING) -> alm [B, nalm] complex."""
+    _check_device(maps)
+    code = _DTYPES[maps.dtype]
+    maps = maps.contiguous()
+    B, n = maps.shape
+    nside = nside_of(n)
+    out = torch.empty((B, nalm(lmax)), dtype=_ALM_DTYPE[code], device=maps.device)
+    return _call("shtx_map2alm", nside, lmax, B, code, maps, out, maps.device)
+
+
+def alm2map_raw(alm, nside, lmax):
+    """alm [B, nalm] complex128/complex64 -> maps [B, Npix] float64/float32."""
+    _check_device(alm)
+    code = _ALM_CODE[alm.dtype]
+    alm = alm.contiguous()
+    B = alm.shape[0]
+    if alm.shape[1] != nalm(lmax):
+        raise ValueError("alm has %d coefficients, lmax=%d needs %d" % (alm.shape[1], lmax, nalm(lmax)))
+    out = torch.empty((B, npix(nside)), dtype=torch.float64 if code == _lib.F64 else torch.float32,
+                      device=alm.device)
+    return _call("shtx_alm2map", nside, lmax, B, code, alm, out, alm.device)
+
+
+def map2alm_backward_raw(grad_alm, nside, lmax, map_dtype):
+    code = _DTYPES[map_dtype]
+    grad_alm = grad_alm.contiguous().to(_ALM_DTYPE[code])
+    B = grad_alm.shape[0]
+    out = torch.empty((B, npix(nside)), dtype=map_dtype, device=grad_alm.device)
+    return _call("shtx_map2alm_backward", nside, lmax, B, code, grad_alm, out, grad_alm.device)
+
+
+def alm2map_backward_raw(grad_map, lmax, alm_dtype):
+    code = _ALM_CODE[alm_dtype]
+    grad_map = grad_map.contiguous().to(torch.float64 if code == _lib.F64 else torch.float32)
+    B, n = grad_map.shape
+    nside = nside_of(n)
+    out = torch.empty((B, nalm(lmax)), dtype=alm_dtype, device=grad_map.device)
+    return _call("shtx_alm2map_backward", nside, lmax, B, code, grad_map, out, grad_map.device)
+
+
+# ------------------------------------------------------------- autograd ops
+class Map2Alm(torch.autograd.Function):
+    """Differentiable analysis; backward is the adjoint kernel chain."""
+
+    @staticmethod
+    def forward(ctx, maps, lmax):
+        ctx.lmax = lmax
+        ctx.nside = nside_of(maps.shape[-1])
+        ctx.map_dtype = maps.dtype
+        return map2alm_raw(maps, lmax)
+
+    @staticmethod
+    def backward(ctx, grad_alm):
+        g = map2alm_backward_raw(grad_alm, ctx.nside, ctx.lmax, ctx.map_dtype)
+        return g, None
+
+
+class Alm2Map(torch.autograd.Function):
+    """Differentiable synthesis; backward is the adjoint kernel chain."""
+
+    @staticmethod
+    def forward(ctx, alm, nside, lmax):
+        ctx.lmax = lmax
+        ctx.alm_dtype = alm.dtype
+        return alm2map_raw(alm, nside, lmax)
+
+    @staticmethod
+    def backward(ctx, grad_map):
+        g = alm2map_backward_raw(grad_map, ctx.lmax, ctx.alm_dtype)
+        return g, None, None
+
+
+def map2alm(maps, lmax):
+    """Analysis of RING maps [..., Npix] (batch of 1-D) -> alm [..., nalm]."""
+    x, squeeze = _as_batched(maps)
+    out = Map2Alm.apply(x, lmax)
+    return out[0] if squeeze else out
+
+
+def alm2map(alm, nside, lmax):
+    """Synthesis of alm [..., nalm] -> RING maps [..., Npix]."""
+    x, squeeze = _as_batched(alm)
+    out = Alm2Map.apply(x, nside, lmax)
+    return out[0] if squeeze else out

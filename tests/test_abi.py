@@ -1,0 +1,93 @@
+"""Host-side checks of the C ABI (no GPU work: validation happens before any
+launch, size queries are closed-form)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2510_01785_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    with open(os.path.join(ROOT, "include", "shtx.h")) as f:
+        text = f.read()
+    return sorted(set(re.findall(r"\b(shtx_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = _lib.lib()
+    decl = declared_functions()
+    assert set(decl) == set(_lib.EXPORTS)
+    for name in decl:
+        assert hasattr(L, name), name
+
+
+def test_status_strings():
+    L = _lib.lib()
+    for s in range(6):
+        assert L.shtx_status_string(s)
+    assert L.shtx_version() >= 100
+
+
+def nalm(l):
+    return (l + 1) * (l + 2) // 2
+
+
+@pytest.mark.parametrize("nside,lmax,batch,dtype", [(32, 95, 1, 0), (1024, 2047, 16, 1), (1024, 2047, 16, 2),
+                                                     (2048, 4095, 1, 0), (1, 0, 3, 1)])
+def test_workspace_closed_form(nside, lmax, batch, dtype):
+    cs = 16 if dtype == 0 else 8
+    up = lambda x: (x + 255) // 256 * 256
+    spec = (lmax + 1) * 2 * nside * batch * cs
+    want = 2 * up(spec) + up(nalm(lmax) * batch * cs)
+    assert _lib.lib().shtx_workspace_bytes(nside, lmax, batch, dtype) == want
+
+
+def test_size_queries_reject_invalid():
+    L = _lib.lib()
+    assert L.shtx_tables_bytes(3, 10) == 0
+    assert L.shtx_tables_bytes(0, 10) == 0
+    assert L.shtx_tables_bytes(8, -1) == 0
+    assert L.shtx_tables_bytes(4096, 10) == 0  # beyond supported nside
+    assert L.shtx_workspace_bytes(8, 10, 0, 0) == 0
+    assert L.shtx_workspace_bytes(8, 10, 1, 7) == 0
+    assert L.shtx_tables_bytes(1024, 2047) > 0
+
+
+FAKE = 0x7F0000000000  # never dereferenced: every call below fails validation
+
+
+@pytest.mark.parametrize("fn", ["shtx_map2alm", "shtx_alm2map", "shtx_map2alm_backward", "shtx_alm2map_backward"])
+def test_validation_before_launch(fn):
+    L = _lib.lib()
+    f = getattr(L, fn)
+    wb = L.shtx_workspace_bytes(8, 15, 2, 1)
+    # bad nside / lmax / batch / dtype
+    assert f(6, 15, 2, 1, FAKE, FAKE, FAKE, FAKE, wb, None) == _lib.ERR_ARG
+    assert f(8, -2, 2, 1, FAKE, FAKE, FAKE, FAKE, wb, None) == _lib.ERR_ARG
+    assert f(8, 15, 0, 1, FAKE, FAKE, FAKE, FAKE, wb, None) == _lib.ERR_ARG
+    assert f(8, 15, 2, 9, FAKE, FAKE, FAKE, FAKE, wb, None) == _lib.ERR_ARG
+    # null pointers
+    assert f(8, 15, 2, 1, None, FAKE, FAKE, FAKE, wb, None) == _lib.ERR_ARG
+    assert f(8, 15, 2, 1, FAKE, None, FAKE, FAKE, wb, None) == _lib.ERR_ARG
+    assert f(8, 15, 2, 1, FAKE, FAKE, None, FAKE, wb, None) == _lib.ERR_ARG
+    assert f(8, 15, 2, 1, FAKE, FAKE, FAKE, None, wb, None) == _lib.ERR_ARG
+    # unaligned workspace
+    assert f(8, 15, 2, 1, FAKE, FAKE, FAKE, FAKE + 8, wb, None) == _lib.ERR_ARG
+    # unsupported nside
+    assert f(4096, 15, 2, 1, FAKE, FAKE, FAKE, FAKE, wb, None) == _lib.ERR_UNSUPPORTED
+    # tables never built for this pointer
+    assert f(8, 15, 2, 1, FAKE, FAKE, FAKE, FAKE, wb, None) == _lib.ERR_TABLES
+
+
+def test_tables_build_validation():
+    L = _lib.lib()
+    assert L.shtx_tables_build(5, 10, FAKE, 1 << 30, None) == _lib.ERR_ARG
+    assert L.shtx_tables_build(8, 10, None, 1 << 30, None) == _lib.ERR_ARG
+    assert L.shtx_tables_build(8, 10, FAKE + 16, 1 << 30, None) == _lib.ERR_ARG
+    assert L.shtx_tables_build(8, 10, FAKE, 16, None) == _lib.ERR_WORKSPACE
+    assert L.shtx_tables_build(4096, 10, FAKE, 1 << 40, None) == _lib.ERR_UNSUPPORTED
+    assert L.shtx_tables_release(FAKE) == _lib.ERR_TABLES
