@@ -12,10 +12,10 @@ namespace shtx {
 
 hipError_t launch_tables_build(int nside, int lmax, void *base, hipStream_t st);
 template <typename TIn, typename T>
-hipError_t launch_ring_fft_fwd(const Tables &, int, const TIn *, const double *, double, cplx<T> *, cplx<T> *,
+hipError_t launch_ring_fft_fwd(Tables, int, const TIn *, const double *, double, cplx<T> *, cplx<T> *,
                                hipStream_t);
 template <typename TOut, typename T>
-hipError_t launch_ring_fft_inv(const Tables &, int, const cplx<T> *, const cplx<T> *, TOut *, hipStream_t);
+hipError_t launch_ring_fft_inv(Tables, int, const cplx<T> *, const cplx<T> *, TOut *, hipStream_t);
 template <typename T>
 hipError_t launch_legendre_fwd_valu(const Tables &, int, const cplx<T> *, const cplx<T> *, cplx<T> *, hipStream_t);
 template <typename T>
@@ -79,7 +79,11 @@ void profile_collect() {
 }
 
 std::mutex g_mu;
-std::unordered_map<const void *, std::pair<int, int>> g_tables;
+struct Registered {
+  int nside, lmax;
+  Tables view;
+};
+std::unordered_map<const void *, Registered> g_tables;
 
 bool valid_geom(int nside, int lmax) {
   if (nside < 1 || (nside & (nside - 1)) != 0) return false;
@@ -88,7 +92,7 @@ bool valid_geom(int nside, int lmax) {
 }
 
 int check_common(int nside, int lmax, int batch, int dtype, const void *in, const void *out, const void *tables,
-                 const void *work, size_t work_bytes) {
+                 const void *work, size_t work_bytes, Tables *view) {
   if (!valid_geom(nside, lmax) || batch < 1) return SHTX_ERR_ARG;
   if (dtype != SHTX_F64 && dtype != SHTX_F32 && dtype != SHTX_BF16) return SHTX_ERR_ARG;
   if (!in || !out || !tables || !work) return SHTX_ERR_ARG;
@@ -97,7 +101,8 @@ int check_common(int nside, int lmax, int batch, int dtype, const void *in, cons
   {
     std::lock_guard<std::mutex> lk(g_mu);
     auto it = g_tables.find(tables);
-    if (it == g_tables.end() || it->second.first != nside || it->second.second != lmax) return SHTX_ERR_TABLES;
+    if (it == g_tables.end() || it->second.nside != nside || it->second.lmax != lmax) return SHTX_ERR_TABLES;
+    *view = it->second.view;
   }
   if (work_bytes < shtx_workspace_bytes(nside, lmax, batch, dtype)) return SHTX_ERR_WORKSPACE;
   return SHTX_OK;
@@ -224,7 +229,7 @@ int shtx_tables_build(int nside, int lmax, void *tables, size_t tables_bytes, vo
   const hipError_t e = launch_tables_build(nside, lmax, tables, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return SHTX_ERR_HIP;
   std::lock_guard<std::mutex> lk(g_mu);
-  g_tables[tables] = std::make_pair(nside, lmax);
+  g_tables[tables] = Registered{nside, lmax, tables_view(tables, nside, lmax)};
   return SHTX_OK;
 }
 
@@ -244,9 +249,9 @@ size_t shtx_workspace_bytes(int nside, int lmax, int batch, int dtype) {
 
 int shtx_map2alm(int nside, int lmax, int batch, int dtype, const void *map, void *alm, const void *tables,
                  void *work, size_t work_bytes, void *stream) {
-  int s = check_common(nside, lmax, batch, dtype, map, alm, tables, work, work_bytes);
+  Tables tb;
+  int s = check_common(nside, lmax, batch, dtype, map, alm, tables, work, work_bytes, &tb);
   if (s != SHTX_OK) return s;
-  const Tables tb = tables_view(tables, nside, lmax);
   hipStream_t st = static_cast<hipStream_t>(stream);
   switch (dtype) {
     case SHTX_F64:
@@ -263,10 +268,10 @@ int shtx_map2alm(int nside, int lmax, int batch, int dtype, const void *map, voi
 
 int shtx_alm2map(int nside, int lmax, int batch, int dtype, const void *alm, void *map, const void *tables,
                  void *work, size_t work_bytes, void *stream) {
-  int s = check_common(nside, lmax, batch, dtype, alm, map, tables, work, work_bytes);
+  Tables tb;
+  int s = check_common(nside, lmax, batch, dtype, alm, map, tables, work, work_bytes, &tb);
   if (s != SHTX_OK) return s;
   if (dtype == SHTX_BF16) return SHTX_ERR_UNSUPPORTED;
-  const Tables tb = tables_view(tables, nside, lmax);
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (dtype == SHTX_F64)
     return run_synthesis<double, double>(tb, batch, static_cast<const double2 *>(alm), static_cast<double *>(map),
@@ -277,9 +282,9 @@ int shtx_alm2map(int nside, int lmax, int batch, int dtype, const void *alm, voi
 
 int shtx_map2alm_backward(int nside, int lmax, int batch, int dtype, const void *grad_alm, void *grad_map,
                           const void *tables, void *work, size_t work_bytes, void *stream) {
-  int s = check_common(nside, lmax, batch, dtype, grad_alm, grad_map, tables, work, work_bytes);
+  Tables tb;
+  int s = check_common(nside, lmax, batch, dtype, grad_alm, grad_map, tables, work, work_bytes, &tb);
   if (s != SHTX_OK) return s;
-  const Tables tb = tables_view(tables, nside, lmax);
   hipStream_t st = static_cast<hipStream_t>(stream);
   const double w = 4.0 * M_PI / (double)tb.npix;
   switch (dtype) {
@@ -297,10 +302,10 @@ int shtx_map2alm_backward(int nside, int lmax, int batch, int dtype, const void 
 
 int shtx_alm2map_backward(int nside, int lmax, int batch, int dtype, const void *grad_map, void *grad_alm,
                           const void *tables, void *work, size_t work_bytes, void *stream) {
-  int s = check_common(nside, lmax, batch, dtype, grad_map, grad_alm, tables, work, work_bytes);
+  Tables tb;
+  int s = check_common(nside, lmax, batch, dtype, grad_map, grad_alm, tables, work, work_bytes, &tb);
   if (s != SHTX_OK) return s;
   if (dtype == SHTX_BF16) return SHTX_ERR_UNSUPPORTED;
-  const Tables tb = tables_view(tables, nside, lmax);
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (dtype == SHTX_F64)
     return run_analysis<double, double>(tb, batch, static_cast<const double *>(grad_map),

@@ -35,16 +35,61 @@ __host__ __device__ inline size_t roots_offset(int i) {
   return (size_t)2 * (size_t)i * (size_t)(i - 1);
 }
 
+// Ring lengths n = 4i whose odd part has a prime factor above this are
+// transformed with Bluestein's chirp-z algorithm (Eq. (17)-(23)) on a
+// power-of-two length; the others with mixed radix 4/2/3/5/7/11/13.
+constexpr int kMaxDirectPrime = 13;
+
+__host__ __device__ inline int largest_odd_prime(int i) {
+  while ((i & 1) == 0 && i > 0) i >>= 1;
+  int big = 1;
+  for (int f = 3; f * f <= i; f += 2)
+    while (i % f == 0) {
+      big = f;
+      i /= f;
+    }
+  if (i > 1) big = i > big ? i : big;
+  return big;
+}
+
+// Bluestein convolution length for ring length 4i, or 0 for mixed radix.
+__host__ __device__ inline int bluestein_len(int i) {
+  if (largest_odd_prime(i) <= kMaxDirectPrime) return 0;
+  const int need = 2 * (4 * i) - 1;
+  int M = 1;
+  while (M < need) M <<= 1;
+  return M;
+}
+
+// Sum of Bluestein lengths of cap rings 1..nside-1 and their maximum.
+inline void bluestein_sizes(int nside, size_t *total, int *mmax) {
+  size_t t = 0;
+  int mx = 0;
+  for (int i = 1; i < nside; ++i) {
+    const int M = bluestein_len(i);
+    t += (size_t)M;
+    mx = M > mx ? M : mx;
+  }
+  *total = t;
+  *mmax = mx;
+}
+
 // Byte offsets of the pieces of the resident table buffer.
 struct TableOffsets {
   size_t rp_n, rp_sN, rp_sS, rp_p0n, rp_p0d;  // int32 [Rp]
+  size_t rp_M, rp_bsoff;                      // int32 [Rp]: Bluestein length (0: mixed radix), offset
   size_t rp_z, rp_sth, rp_w;                  // double [Rp]
   size_t coefA, coefC;                        // double [nalm]
   size_t seed_l;                              // int32 [(L+1) * Rp]
   size_t seed_v;                              // double2 [(L+1) * Rp]
-  size_t roots64;                             // double2 [2N(N+1)]
+  size_t roots64;                             // double2 [2N(N+1)]  per ring length 4i
   size_t roots32;                             // float2  [2N(N+1)]
+  size_t chirp64, chirp32;                    // Bluestein chirps, same layout as roots
+  size_t bhat64, bhat32, bhat_tmp;            // FFT of the conjugate chirp, [sum M_i]
+  size_t rootsP64, rootsP32;                  // roots of the largest Bluestein length
   size_t total;
+  size_t nbhat;
+  int mmax_bs;
 };
 
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
@@ -54,6 +99,7 @@ inline TableOffsets table_offsets(int nside, int lmax) {
   const size_t Rp = 2 * (size_t)nside;
   const size_t nalm = nalm_of(lmax);
   const size_t nroots = roots_offset(nside + 1);
+  bluestein_sizes(nside, &o.nbhat, &o.mmax_bs);
   size_t off = 0;
   auto take = [&](size_t bytes) {
     size_t here = off;
@@ -65,6 +111,8 @@ inline TableOffsets table_offsets(int nside, int lmax) {
   o.rp_sS = take(Rp * 4);
   o.rp_p0n = take(Rp * 4);
   o.rp_p0d = take(Rp * 4);
+  o.rp_M = take(Rp * 4);
+  o.rp_bsoff = take(Rp * 4);
   o.rp_z = take(Rp * 8);
   o.rp_sth = take(Rp * 8);
   o.rp_w = take(Rp * 8);
@@ -74,19 +122,28 @@ inline TableOffsets table_offsets(int nside, int lmax) {
   o.seed_v = take((size_t)(lmax + 1) * Rp * 16);
   o.roots64 = take(nroots * 16);
   o.roots32 = take(nroots * 8);
+  o.chirp64 = take(nroots * 16);
+  o.chirp32 = take(nroots * 8);
+  o.bhat64 = take(o.nbhat * 16);
+  o.bhat32 = take(o.nbhat * 8);
+  o.bhat_tmp = take(o.nbhat * 16);
+  o.rootsP64 = take((size_t)o.mmax_bs * 16);
+  o.rootsP32 = take((size_t)o.mmax_bs * 8);
   o.total = off;
   return o;
 }
 
 struct Tables {
-  int nside, lmax, npairs, npix;
-  const int *rp_n, *rp_sN, *rp_sS, *rp_p0n, *rp_p0d;
+  int nside, lmax, npairs, npix, mmax_bs;
+  const int *rp_n, *rp_sN, *rp_sS, *rp_p0n, *rp_p0d, *rp_M, *rp_bsoff;
   const double *rp_z, *rp_sth, *rp_w;
   const double *coefA, *coefC;
   const int *seed_l;
   const double2 *seed_v;
   const double2 *roots64;
   const float2 *roots32;
+  const double2 *chirp64, *bhat64, *rootsP64;
+  const float2 *chirp32, *bhat32, *rootsP32;
 };
 
 inline Tables tables_view(const void *base, int nside, int lmax) {
@@ -97,11 +154,14 @@ inline Tables tables_view(const void *base, int nside, int lmax) {
   t.lmax = lmax;
   t.npairs = 2 * nside;
   t.npix = 12 * nside * nside;
+  t.mmax_bs = o.mmax_bs;
   t.rp_n = reinterpret_cast<const int *>(b + o.rp_n);
   t.rp_sN = reinterpret_cast<const int *>(b + o.rp_sN);
   t.rp_sS = reinterpret_cast<const int *>(b + o.rp_sS);
   t.rp_p0n = reinterpret_cast<const int *>(b + o.rp_p0n);
   t.rp_p0d = reinterpret_cast<const int *>(b + o.rp_p0d);
+  t.rp_M = reinterpret_cast<const int *>(b + o.rp_M);
+  t.rp_bsoff = reinterpret_cast<const int *>(b + o.rp_bsoff);
   t.rp_z = reinterpret_cast<const double *>(b + o.rp_z);
   t.rp_sth = reinterpret_cast<const double *>(b + o.rp_sth);
   t.rp_w = reinterpret_cast<const double *>(b + o.rp_w);
@@ -111,6 +171,12 @@ inline Tables tables_view(const void *base, int nside, int lmax) {
   t.seed_v = reinterpret_cast<const double2 *>(b + o.seed_v);
   t.roots64 = reinterpret_cast<const double2 *>(b + o.roots64);
   t.roots32 = reinterpret_cast<const float2 *>(b + o.roots32);
+  t.chirp64 = reinterpret_cast<const double2 *>(b + o.chirp64);
+  t.chirp32 = reinterpret_cast<const float2 *>(b + o.chirp32);
+  t.bhat64 = reinterpret_cast<const double2 *>(b + o.bhat64);
+  t.bhat32 = reinterpret_cast<const float2 *>(b + o.bhat32);
+  t.rootsP64 = reinterpret_cast<const double2 *>(b + o.rootsP64);
+  t.rootsP32 = reinterpret_cast<const float2 *>(b + o.rootsP32);
   return t;
 }
 
@@ -133,10 +199,20 @@ template <typename C> __device__ __forceinline__ C cmul(C a, C b) {
 }
 template <typename C> __device__ __forceinline__ C cconj(C a) { return cmk<C>(a.x, -a.y); }
 
-// Root table of the compute precision.
-template <typename T> __device__ __forceinline__ const cplx<T> *roots_of(const Tables &t);
-template <> __device__ __forceinline__ const float2 *roots_of<float>(const Tables &t) { return t.roots32; }
-template <> __device__ __forceinline__ const double2 *roots_of<double>(const Tables &t) { return t.roots64; }
+// Tables of the compute precision.
+template <typename T> struct TabOf;
+template <> struct TabOf<float> {
+  __device__ static const float2 *roots(const Tables &t) { return t.roots32; }
+  __device__ static const float2 *chirp(const Tables &t) { return t.chirp32; }
+  __device__ static const float2 *bhat(const Tables &t) { return t.bhat32; }
+  __device__ static const float2 *rootsP(const Tables &t) { return t.rootsP32; }
+};
+template <> struct TabOf<double> {
+  __device__ static const double2 *roots(const Tables &t) { return t.roots64; }
+  __device__ static const double2 *chirp(const Tables &t) { return t.chirp64; }
+  __device__ static const double2 *bhat(const Tables &t) { return t.bhat64; }
+  __device__ static const double2 *rootsP(const Tables &t) { return t.rootsP64; }
+};
 
 // exp(sign * i * pi * red / den) for an exactly reduced integer red in
 // [0, 2*den), evaluated in the compute precision.

@@ -20,24 +20,24 @@
 
 namespace shtx {
 
-constexpr int kFftThreads = 512;
-constexpr int kFftOutMax = 16;  // kFftThreads * kFftOutMax complex values per workgroup
+constexpr int kFftOutMax = 16;  // complex values per thread per stage
 
 // Stage of radix 4 (span p, a power of two): butterfly i of channel c reads
 // x[i + r n/4] (r = 0..3), twiddles them by w^{r k n/(4p)} (k = i mod p) and
-// writes y[4(i-k) + k + q p] = sum_r u_r (-i)^{qr}.
-template <typename T>
+// writes y[4(i-k) + k + q p] = sum_r u_r (-i)^{qr}.  Roots are read as
+// roots[e * rs] from a table of length n * rs.
+template <typename T, int NT>
 __device__ __forceinline__ void stage_r4(cplx<T> *buf, int n, int G, int p, int lp,
-                                         const cplx<T> *__restrict__ roots) {
+                                         const cplx<T> *__restrict__ roots, int rs) {
   using C = cplx<T>;
   constexpr int NB = kFftOutMax / 4;
   const int Tq = n >> 2;
   const int nb = G * Tq;
-  const int step = n >> (lp + 2);
+  const int step = (n >> (lp + 2)) * rs;
   C v[NB][4];
 #pragma unroll
   for (int s = 0; s < NB; ++s) {
-    const int b = threadIdx.x + s * kFftThreads;
+    const int b = threadIdx.x + s * NT;
     if (b < nb) {
       const int c = b / Tq, i = b - c * Tq;
       const int k = i & (p - 1);
@@ -59,7 +59,7 @@ __device__ __forceinline__ void stage_r4(cplx<T> *buf, int n, int G, int p, int 
   __syncthreads();
 #pragma unroll
   for (int s = 0; s < NB; ++s) {
-    const int b = threadIdx.x + s * kFftThreads;
+    const int b = threadIdx.x + s * NT;
     if (b < nb) {
       const int c = b / Tq, i = b - c * Tq;
       const int k = i & (p - 1);
@@ -74,18 +74,18 @@ __device__ __forceinline__ void stage_r4(cplx<T> *buf, int n, int G, int p, int 
 }
 
 // Stage of radix 2 (span p, a power of two).
-template <typename T>
+template <typename T, int NT>
 __device__ __forceinline__ void stage_r2(cplx<T> *buf, int n, int G, int p, int lp,
-                                         const cplx<T> *__restrict__ roots) {
+                                         const cplx<T> *__restrict__ roots, int rs) {
   using C = cplx<T>;
   constexpr int NB = kFftOutMax / 2;
   const int Th = n >> 1;
   const int nb = G * Th;
-  const int step = n >> (lp + 1);
+  const int step = (n >> (lp + 1)) * rs;
   C v[NB][2];
 #pragma unroll
   for (int s = 0; s < NB; ++s) {
-    const int b = threadIdx.x + s * kFftThreads;
+    const int b = threadIdx.x + s * NT;
     if (b < nb) {
       const int c = b / Th, i = b - c * Th;
       const int k = i & (p - 1);
@@ -99,7 +99,7 @@ __device__ __forceinline__ void stage_r2(cplx<T> *buf, int n, int G, int p, int 
   __syncthreads();
 #pragma unroll
   for (int s = 0; s < NB; ++s) {
-    const int b = threadIdx.x + s * kFftThreads;
+    const int b = threadIdx.x + s * NT;
     if (b < nb) {
       const int c = b / Th, i = b - c * Th;
       const int k = i & (p - 1);
@@ -113,7 +113,8 @@ __device__ __forceinline__ void stage_r2(cplx<T> *buf, int n, int G, int p, int 
 
 // Stage of odd radix R (span p): thread per output,
 //   y[g pR + q p + k] = sum_r x[g p + k + r n/R] w^{r (n/(pR)) (k + q p)}.
-template <typename T>
+// Used for R <= kMaxDirectPrime only.
+template <typename T, int NT>
 __device__ __noinline__ void stage_odd(cplx<T> *buf, int n, int G, int p, int R,
                                        const cplx<T> *__restrict__ roots) {
   using C = cplx<T>;
@@ -124,7 +125,7 @@ __device__ __noinline__ void stage_odd(cplx<T> *buf, int n, int G, int p, int R,
   C out[kFftOutMax];
 #pragma unroll
   for (int s = 0; s < kFftOutMax; ++s) {
-    const int o = threadIdx.x + s * kFftThreads;
+    const int o = threadIdx.x + s * NT;
     if (o < tot) {
       const int c = o / n;
       const int oo = o - c * n;
@@ -147,27 +148,39 @@ __device__ __noinline__ void stage_odd(cplx<T> *buf, int n, int G, int p, int R,
   __syncthreads();
 #pragma unroll
   for (int s = 0; s < kFftOutMax; ++s) {
-    const int o = threadIdx.x + s * kFftThreads;
+    const int o = threadIdx.x + s * NT;
     if (o < tot) buf[o] = out[s];
   }
   __syncthreads();
 }
 
-// In-place forward DFT (exp(-2 pi i jk/n)) of G channels of length n = 4i
-// stored channel-major in LDS: Stockham autosort, radix-4 stages over the
-// power-of-two part of n, one radix-2 stage if needed, then one stage per
-// remaining odd prime factor.  Natural-order output.
-template <typename T>
-__device__ void fft_lds(cplx<T> *buf, int n, int G, const cplx<T> *__restrict__ roots) {
+// Radix-4/2 Stockham FFT of G channels of power-of-two length n.
+template <typename T, int NT>
+__device__ void fft_pow2(cplx<T> *buf, int n, int G, const cplx<T> *__restrict__ roots, int rs) {
   int rem = n, p = 1, lp = 0;
   while ((rem & 3) == 0) {
-    stage_r4<T>(buf, n, G, p, lp, roots);
+    stage_r4<T, NT>(buf, n, G, p, lp, roots, rs);
+    p <<= 2;
+    lp += 2;
+    rem >>= 2;
+  }
+  if (rem == 2) stage_r2<T, NT>(buf, n, G, p, lp, roots, rs);
+}
+
+// Mixed-radix Stockham FFT of G channels of length n = 4i: radix-4 stages over
+// the power-of-two part, one radix-2 stage if needed, then one direct stage
+// per remaining odd prime factor (all <= kMaxDirectPrime on this path).
+template <typename T, int NT>
+__device__ void fft_mixed(cplx<T> *buf, int n, int G, const cplx<T> *__restrict__ roots) {
+  int rem = n, p = 1, lp = 0;
+  while ((rem & 3) == 0) {
+    stage_r4<T, NT>(buf, n, G, p, lp, roots, 1);
     p <<= 2;
     lp += 2;
     rem >>= 2;
   }
   if ((rem & 1) == 0) {
-    stage_r2<T>(buf, n, G, p, lp, roots);
+    stage_r2<T, NT>(buf, n, G, p, lp, roots, 1);
     p <<= 1;
     lp += 1;
     rem >>= 1;
@@ -179,16 +192,53 @@ __device__ void fft_lds(cplx<T> *buf, int n, int G, const cplx<T> *__restrict__ 
         R = r;
         break;
       }
-    stage_odd<T>(buf, n, G, p, R, roots);
+    stage_odd<T, NT>(buf, n, G, p, R, roots);
     p *= R;
     rem /= R;
   }
 }
 
-template <typename TIn, typename T>
-__global__ void __launch_bounds__(kFftThreads)
-    k_ring_fft_fwd(Tables tb, int B, int G, const TIn *__restrict__ map, const double *__restrict__ wtab,
-                   double wscale, cplx<T> *__restrict__ XE, cplx<T> *__restrict__ XO) {
+// Bluestein DFT of one channel of length n (Eq. (17)-(23)): with the chirp
+// c_j = exp(-i pi j^2/n), X_k = c_k sum_j (x_j c_j) conj(c_{k-j}); the
+// convolution is done cyclically on the power-of-two length M >= 2n-1 with
+// the precomputed transform bhat of conj(c) and two radix-4 FFTs in LDS (the
+// inverse one through conjugation).  On return buf[0..n) holds X.
+template <typename T, int NT>
+__device__ void fft_bluestein(cplx<T> *buf, int n, int M, const cplx<T> *__restrict__ chirp,
+                              const cplx<T> *__restrict__ bhat, const cplx<T> *__restrict__ rootsP, int rs) {
+  using C = cplx<T>;
+  for (int j = threadIdx.x; j < M; j += NT) buf[j] = (j < n) ? cmul(buf[j], chirp[j]) : cmk<C>(0, 0);
+  __syncthreads();
+  fft_pow2<T, NT>(buf, M, 1, rootsP, rs);
+  for (int j = threadIdx.x; j < M; j += NT) buf[j] = cconj(cmul(buf[j], bhat[j]));
+  __syncthreads();
+  fft_pow2<T, NT>(buf, M, 1, rootsP, rs);
+  const T inv = (T)1 / (T)M;
+  for (int j = threadIdx.x; j < n; j += NT) {
+    const C v = cconj(buf[j]);
+    buf[j] = cmul(chirp[j], cmk<C>(v.x * inv, v.y * inv));
+  }
+  __syncthreads();
+}
+
+// Forward DFT of gc channels of ring-pair p held in buf (channel-major).
+template <typename T, int NT>
+__device__ __forceinline__ void ring_dft(const Tables &tb, int p, int M, cplx<T> *buf, int n, int gc) {
+  if (M == 0) {
+    fft_mixed<T, NT>(buf, n, gc, TabOf<T>::roots(tb) + roots_offset(n >> 2));
+  } else {
+    // Bluestein rings run one channel at a time (gc == 1)
+    const size_t co = roots_offset(n >> 2);
+    fft_bluestein<T, NT>(buf, n, M, TabOf<T>::chirp(tb) + co, TabOf<T>::bhat(tb) + tb.rp_bsoff[p],
+                         TabOf<T>::rootsP(tb), tb.mmax_bs / M);
+  }
+}
+
+template <typename TIn, typename T, int NT>
+__global__ void __launch_bounds__(NT)
+    k_ring_fft_fwd(Tables tb, int B, int G, int use_bs, const TIn *__restrict__ map,
+                   const double *__restrict__ wtab, double wscale, cplx<T> *__restrict__ XE,
+                   cplx<T> *__restrict__ XO) {
   using C = cplx<T>;
   extern __shared__ unsigned char smem_raw[];
   C *buf = reinterpret_cast<C *>(smem_raw);
@@ -197,14 +247,14 @@ __global__ void __launch_bounds__(kFftThreads)
   const int sN = tb.rp_sN[p], sS = tb.rp_sS[p];
   const bool equator = (sN == sS);
   const int L = tb.lmax, M = L + 1;
-  const int ringi = (n >> 2);  // n = 4i
-  const C *roots = roots_of<T>(tb) + roots_offset(ringi);
   const T w = (T)(wtab ? wtab[p] * wscale : wscale);
   const int num = tb.rp_p0n[p], den = tb.rp_p0d[p];
   const size_t npix = (size_t)tb.npix;
-  for (int b0 = 0; b0 < B; b0 += G) {
-    const int gc = min(G, B - b0);
-    for (int j = threadIdx.x; j < gc * n; j += kFftThreads) {
+  const int Mbs = use_bs ? tb.rp_M[p] : 0;
+  const int Gp = Mbs ? 1 : G;
+  for (int b0 = 0; b0 < B; b0 += Gp) {
+    const int gc = min(Gp, B - b0);
+    for (int j = threadIdx.x; j < gc * n; j += NT) {
       const int c = j / n, jj = j - c * n;
       const TIn *row = map + (size_t)(b0 + c) * npix;
       const T fN = load_as<T, TIn>(row + sN + jj);
@@ -212,9 +262,9 @@ __global__ void __launch_bounds__(kFftThreads)
       buf[j] = cmk<C>(fN + fS, fN - fS);
     }
     __syncthreads();
-    fft_lds<T>(buf, n, gc, roots);
+    ring_dft<T, NT>(tb, p, Mbs, buf, n, gc);
     // E/O spectra for m = 0..L, channel fastest for contiguous stores
-    for (int t = threadIdx.x; t < M * gc; t += kFftThreads) {
+    for (int t = threadIdx.x; t < M * gc; t += NT) {
       const int m = t / gc, c = t - m * gc;
       const int k = m % n;
       const int kc = (k == 0) ? 0 : n - k;
@@ -235,10 +285,10 @@ __global__ void __launch_bounds__(kFftThreads)
   }
 }
 
-template <typename TOut, typename T>
-__global__ void __launch_bounds__(kFftThreads)
-    k_ring_fft_inv(Tables tb, int B, int G, const cplx<T> *__restrict__ GN, const cplx<T> *__restrict__ GS,
-                   TOut *__restrict__ map) {
+template <typename TOut, typename T, int NT>
+__global__ void __launch_bounds__(NT)
+    k_ring_fft_inv(Tables tb, int B, int G, int use_bs, const cplx<T> *__restrict__ GN,
+                   const cplx<T> *__restrict__ GS, TOut *__restrict__ map) {
   using C = cplx<T>;
   extern __shared__ unsigned char smem_raw[];
   C *buf = reinterpret_cast<C *>(smem_raw);
@@ -247,12 +297,13 @@ __global__ void __launch_bounds__(kFftThreads)
   const int sN = tb.rp_sN[p], sS = tb.rp_sS[p];
   const bool equator = (sN == sS);
   const int L = tb.lmax, M = L + 1;
-  const C *roots = roots_of<T>(tb) + roots_offset(n >> 2);
   const int num = tb.rp_p0n[p], den = tb.rp_p0d[p];
   const size_t npix = (size_t)tb.npix;
-  for (int b0 = 0; b0 < B; b0 += G) {
-    const int gc = min(G, B - b0);
-    for (int j = threadIdx.x; j < gc * n; j += kFftThreads) {
+  const int Mbs = use_bs ? tb.rp_M[p] : 0;
+  const int Gp = Mbs ? 1 : G;
+  for (int b0 = 0; b0 < B; b0 += Gp) {
+    const int gc = min(Gp, B - b0);
+    for (int j = threadIdx.x; j < gc * n; j += NT) {
       const int c = j / n, k = j - c * n;
       C cn = cmk<C>(0, 0), cs = cmk<C>(0, 0);
       // positive frequencies m = k (mod n)
@@ -283,8 +334,8 @@ __global__ void __launch_bounds__(kFftThreads)
       buf[j] = cmk<C>(cn.x - cs.y, -(cn.y + cs.x));
     }
     __syncthreads();
-    fft_lds<T>(buf, n, gc, roots);
-    for (int j = threadIdx.x; j < gc * n; j += kFftThreads) {
+    ring_dft<T, NT>(tb, p, Mbs, buf, n, gc);
+    for (int j = threadIdx.x; j < gc * n; j += NT) {
       const int c = j / n, jj = j - c * n;
       const C F = buf[j];  // IDFT(h) = conj(F): f_N = F.x, f_S = -F.y
       TOut *row = map + (size_t)(b0 + c) * npix;
@@ -295,57 +346,74 @@ __global__ void __launch_bounds__(kFftThreads)
   }
 }
 
-// Channels per FFT group: as many as fit kFftThreads*kFftOutMax points and
-// the LDS budget.
-template <typename T> int fft_group(int nside, int B) {
-  const int nmax = 4 * nside;
-  int G = (kFftThreads * kFftOutMax) / nmax;
-  const int lds_cap = (128 * 1024) / (int)(nmax * sizeof(cplx<T>));
-  if (G > lds_cap) G = lds_cap;
-  if (G > B) G = B;
-  if (G > 16) G = 16;
-  return G < 1 ? 1 : G;
+// Launch geometry: threads per workgroup, channels per mixed-radix group and
+// LDS bytes.  Bluestein rings need M complex values of LDS; precisions or
+// sizes where that does not fit 128 KB (FP64 at nside 2048) take the
+// mixed-radix path for every ring (use_bs = 0).
+template <typename T> struct FftCfg {
+  static constexpr int NT = sizeof(T) == 8 ? 512 : 1024;
+};
+
+template <typename T> bool fft_geometry(const Tables &tb, int B, int *G, size_t *lds) {
+  constexpr int NT = FftCfg<T>::NT;
+  const int nmax = 4 * tb.nside;
+  const int cap = NT * kFftOutMax;  // complex values one stage can hold
+  int g = cap / nmax;
+  const int lds_cap = (64 * 1024) / (int)(nmax * sizeof(cplx<T>));
+  if (g > lds_cap) g = lds_cap;
+  if (g > B) g = B;
+  if (g > 16) g = 16;
+  if (g < 1) g = 1;
+  *G = g;
+  size_t need = (size_t)g * nmax;
+  const bool use_bs = tb.mmax_bs > 0 && tb.mmax_bs <= cap && (size_t)tb.mmax_bs * sizeof(cplx<T>) <= 128 * 1024;
+  if (use_bs && (size_t)tb.mmax_bs > need) need = tb.mmax_bs;
+  *lds = need * sizeof(cplx<T>);
+  return use_bs;
 }
 
 template <typename TIn, typename T>
-hipError_t launch_ring_fft_fwd(const Tables &tb, int B, const TIn *map, const double *wtab, double wscale,
-                               cplx<T> *XE, cplx<T> *XO, hipStream_t st) {
-  const int G = fft_group<T>(tb.nside, B);
-  const size_t lds = (size_t)G * 4 * tb.nside * sizeof(cplx<T>);
-  auto kern = k_ring_fft_fwd<TIn, T>;
+hipError_t launch_ring_fft_fwd(Tables tb, int B, const TIn *map, const double *wtab, double wscale, cplx<T> *XE,
+                               cplx<T> *XO, hipStream_t st) {
+  constexpr int NT = FftCfg<T>::NT;
+  int G;
+  size_t lds;
+  const int use_bs = fft_geometry<T>(tb, B, &G, &lds) ? 1 : 0;
+  auto kern = k_ring_fft_fwd<TIn, T, NT>;
   if (lds > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(kern, dim3(tb.npairs), dim3(kFftThreads), lds, st, tb, B, G, map, wtab, wscale, XE, XO);
+  hipLaunchKernelGGL(kern, dim3(tb.npairs), dim3(NT), lds, st, tb, B, G, use_bs, map, wtab, wscale, XE, XO);
   return hipGetLastError();
 }
 
 template <typename TOut, typename T>
-hipError_t launch_ring_fft_inv(const Tables &tb, int B, const cplx<T> *GN, const cplx<T> *GS, TOut *map,
-                               hipStream_t st) {
-  const int G = fft_group<T>(tb.nside, B);
-  const size_t lds = (size_t)G * 4 * tb.nside * sizeof(cplx<T>);
-  auto kern = k_ring_fft_inv<TOut, T>;
+hipError_t launch_ring_fft_inv(Tables tb, int B, const cplx<T> *GN, const cplx<T> *GS, TOut *map, hipStream_t st) {
+  constexpr int NT = FftCfg<T>::NT;
+  int G;
+  size_t lds;
+  const int use_bs = fft_geometry<T>(tb, B, &G, &lds) ? 1 : 0;
+  auto kern = k_ring_fft_inv<TOut, T, NT>;
   if (lds > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(kern, dim3(tb.npairs), dim3(kFftThreads), lds, st, tb, B, G, GN, GS, map);
+  hipLaunchKernelGGL(kern, dim3(tb.npairs), dim3(NT), lds, st, tb, B, G, use_bs, GN, GS, map);
   return hipGetLastError();
 }
 
-template hipError_t launch_ring_fft_fwd<double, double>(const Tables &, int, const double *, const double *,
-                                                        double, double2 *, double2 *, hipStream_t);
-template hipError_t launch_ring_fft_fwd<float, float>(const Tables &, int, const float *, const double *, double,
-                                                      float2 *, float2 *, hipStream_t);
-template hipError_t launch_ring_fft_fwd<bf16_t, float>(const Tables &, int, const bf16_t *, const double *,
-                                                       double, float2 *, float2 *, hipStream_t);
-template hipError_t launch_ring_fft_inv<double, double>(const Tables &, int, const double2 *, const double2 *,
-                                                        double *, hipStream_t);
-template hipError_t launch_ring_fft_inv<float, float>(const Tables &, int, const float2 *, const float2 *, float *,
+template hipError_t launch_ring_fft_fwd<double, double>(Tables, int, const double *, const double *, double,
+                                                        double2 *, double2 *, hipStream_t);
+template hipError_t launch_ring_fft_fwd<float, float>(Tables, int, const float *, const double *, double, float2 *,
+                                                      float2 *, hipStream_t);
+template hipError_t launch_ring_fft_fwd<bf16_t, float>(Tables, int, const bf16_t *, const double *, double,
+                                                       float2 *, float2 *, hipStream_t);
+template hipError_t launch_ring_fft_inv<double, double>(Tables, int, const double2 *, const double2 *, double *,
+                                                        hipStream_t);
+template hipError_t launch_ring_fft_inv<float, float>(Tables, int, const float2 *, const float2 *, float *,
                                                       hipStream_t);
-template hipError_t launch_ring_fft_inv<bf16_t, float>(const Tables &, int, const float2 *, const float2 *,
-                                                       bf16_t *, hipStream_t);
+template hipError_t launch_ring_fft_inv<bf16_t, float>(Tables, int, const float2 *, const float2 *, bf16_t *,
+                                                       hipStream_t);
 
 }  // namespace shtx

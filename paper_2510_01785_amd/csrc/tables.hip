@@ -16,8 +16,8 @@
 
 namespace shtx {
 
-__global__ void k_ring_pairs(int N, int *rp_n, int *rp_sN, int *rp_sS, int *p0n, int *p0d,
-                             double *z_out, double *sth_out, double *w_out) {
+__global__ void k_ring_pairs(int N, int *rp_n, int *rp_sN, int *rp_sS, int *p0n, int *p0d, int *rp_M,
+                             int *rp_bsoff, double *z_out, double *sth_out, double *w_out) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= 2 * N) return;
   const int i = p + 1;  // north ring number, 1 .. 2N
@@ -44,6 +44,14 @@ __global__ void k_ring_pairs(int N, int *rp_n, int *rp_sN, int *rp_sS, int *p0n,
   }
   // south partner 4N - i: same length and phi0; RING start by symmetry
   const int sS = (i == 2 * N) ? sN : (int)(npix - (long long)sN - n);
+  // Bluestein length and offset of this ring length in the chirp-transform table
+  int M = 0, off = 0;
+  if (i < N) {
+    M = bluestein_len(i);
+    for (int j = 1; j < i; ++j) off += bluestein_len(j);
+  }
+  rp_M[p] = M;
+  rp_bsoff[p] = off;
   rp_n[p] = n;
   rp_sN[p] = sN;
   rp_sS[p] = sS;
@@ -171,6 +179,83 @@ __global__ void k_roots(int N, double2 *r64, float2 *r32) {
   r32[o] = make_float2((float)c, (float)-s);
 }
 
+// Bluestein chirp c_j = exp(-i pi j^2 / n) for j < n = 4i (Eq. (19)), with
+// j^2 reduced modulo 2n exactly.
+__global__ void k_chirp(int N, double2 *c64, float2 *c32) {
+  const int i = blockIdx.y + 1;
+  if (bluestein_len(i) == 0) return;
+  const int n = 4 * i;
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const int r = (int)(((long long)j * j) % (2 * n));
+  double s, c;
+  sincospi((double)r / (double)n, &s, &c);
+  const size_t o = roots_offset(i) + j;
+  c64[o] = make_double2(c, -s);
+  c32[o] = make_float2((float)c, (float)-s);
+}
+
+// b_j = conj(c_{|j|}) for |j| < n, wrapped onto length M, zero elsewhere.
+__global__ void k_bhat_init(int N, const int *rp_bsoff, const double2 *c64, double2 *buf) {
+  const int i = blockIdx.y + 1;
+  const int M = bluestein_len(i);
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (M == 0 || j >= M) return;
+  const int n = 4 * i;
+  const double2 *c = c64 + roots_offset(i);
+  double2 v = make_double2(0.0, 0.0);
+  if (j < n)
+    v = make_double2(c[j].x, -c[j].y);
+  else if (j > M - n)
+    v = make_double2(c[M - j].x, -c[M - j].y);
+  buf[rp_bsoff[i - 1] + j] = v;
+}
+
+// One radix-2 Stockham stage (span p = 2^s) of the length-M forward FFT of
+// every Bluestein ring, FP64, global memory ping-pong; rings whose FFT has
+// fewer stages copy through so that all results end in the same buffer.
+__global__ void k_bhat_fft_stage(int N, int s, const int *rp_bsoff, const double2 *src, double2 *dst) {
+  const int i = blockIdx.y + 1;
+  const int M = bluestein_len(i);
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (M == 0 || b >= M / 2) return;
+  const int off = rp_bsoff[i - 1];
+  const int h = M / 2;
+  if ((1 << s) >= M) {
+    dst[off + b] = src[off + b];
+    dst[off + b + h] = src[off + b + h];
+    return;
+  }
+  const int p = 1 << s;
+  const int k = b & (p - 1);
+  double sn, cs;
+  sincospi((double)k / (double)p, &sn, &cs);  // exp(-2 pi i k / (2p))
+  const double2 u0 = src[off + b];
+  const double2 x1 = src[off + b + h];
+  const double2 u1 = make_double2(x1.x * cs + x1.y * sn, x1.y * cs - x1.x * sn);
+  const int o = ((b - k) << 1) + k;
+  dst[off + o] = make_double2(u0.x + u1.x, u0.y + u1.y);
+  dst[off + o + p] = make_double2(u0.x - u1.x, u0.y - u1.y);
+}
+
+__global__ void k_bhat_finish(size_t nb, const double2 *src, double2 *b64, float2 *b32) {
+  const size_t j = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= nb) return;
+  const double2 v = src[j];
+  b64[j] = v;
+  b32[j] = make_float2((float)v.x, (float)v.y);
+}
+
+// Roots exp(-2 pi i k / M) of the largest Bluestein length.
+__global__ void k_rootsP(int M, double2 *r64, float2 *r32) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= M) return;
+  double s, c;
+  sincospi(2.0 * (double)k / (double)M, &s, &c);
+  r64[k] = make_double2(c, -s);
+  r32[k] = make_float2((float)c, (float)-s);
+}
+
 hipError_t launch_tables_build(int nside, int lmax, void *base, hipStream_t st) {
   const TableOffsets o = table_offsets(nside, lmax);
   char *b = static_cast<char *>(base);
@@ -178,7 +263,8 @@ hipError_t launch_tables_build(int nside, int lmax, void *base, hipStream_t st) 
   auto I = [&](size_t off) { return reinterpret_cast<int *>(b + off); };
   auto D = [&](size_t off) { return reinterpret_cast<double *>(b + off); };
   hipLaunchKernelGGL(k_ring_pairs, dim3((Rp + 255) / 256), dim3(256), 0, st, nside, I(o.rp_n), I(o.rp_sN),
-                     I(o.rp_sS), I(o.rp_p0n), I(o.rp_p0d), D(o.rp_z), D(o.rp_sth), D(o.rp_w));
+                     I(o.rp_sS), I(o.rp_p0n), I(o.rp_p0d), I(o.rp_M), I(o.rp_bsoff), D(o.rp_z), D(o.rp_sth),
+                     D(o.rp_w));
   hipLaunchKernelGGL(k_coefs, dim3((lmax + 1 + 63) / 64), dim3(64), 0, st, lmax, D(o.coefA), D(o.coefC));
   double2 *sv = reinterpret_cast<double2 *>(b + o.seed_v);
   hipLaunchKernelGGL(k_lambda_mm, dim3((Rp + 63) / 64), dim3(64), 0, st, lmax, Rp, D(o.rp_sth), sv);
@@ -186,6 +272,26 @@ hipError_t launch_tables_build(int nside, int lmax, void *base, hipStream_t st) 
                      D(o.coefA), I(o.seed_l), sv);
   hipLaunchKernelGGL(k_roots, dim3((4 * nside + 255) / 256, nside), dim3(256), 0, st, nside,
                      reinterpret_cast<double2 *>(b + o.roots64), reinterpret_cast<float2 *>(b + o.roots32));
+  if (o.mmax_bs > 0) {
+    auto D2 = [&](size_t off) { return reinterpret_cast<double2 *>(b + off); };
+    auto F2 = [&](size_t off) { return reinterpret_cast<float2 *>(b + off); };
+    const int ncap = nside - 1;
+    hipLaunchKernelGGL(k_chirp, dim3((4 * nside + 255) / 256, ncap), dim3(256), 0, st, nside, D2(o.chirp64),
+                       F2(o.chirp32));
+    hipLaunchKernelGGL(k_bhat_init, dim3((o.mmax_bs + 255) / 256, ncap), dim3(256), 0, st, nside, I(o.rp_bsoff),
+                       D2(o.chirp64), D2(o.bhat_tmp));
+    int S = 0;
+    while ((1 << S) < o.mmax_bs) ++S;
+    double2 *bufs[2] = {D2(o.bhat_tmp), D2(o.bhat64)};
+    for (int s = 0; s < S; ++s)
+      hipLaunchKernelGGL(k_bhat_fft_stage, dim3((o.mmax_bs / 2 + 255) / 256, ncap), dim3(256), 0, st, nside, s,
+                         I(o.rp_bsoff), bufs[s & 1], bufs[(s + 1) & 1]);
+    const double2 *res = bufs[S & 1];
+    hipLaunchKernelGGL(k_bhat_finish, dim3((unsigned)((o.nbhat + 255) / 256)), dim3(256), 0, st, o.nbhat, res,
+                       D2(o.bhat64), F2(o.bhat32));
+    hipLaunchKernelGGL(k_rootsP, dim3((o.mmax_bs + 255) / 256), dim3(256), 0, st, o.mmax_bs, D2(o.rootsP64),
+                       F2(o.rootsP32));
+  }
   return hipGetLastError();
 }
 

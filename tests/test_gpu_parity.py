@@ -49,6 +49,9 @@ CASES = [
     (32, 95, 4, torch.float32),
     (64, 191, 16, torch.float32),
     (64, 127, 3, torch.float64),
+    # every cap length up to 4*127 (Bluestein for lengths with a prime factor > 13)
+    (128, 255, 2, torch.float64),
+    (256, 300, 2, torch.float32),
 ]
 
 
