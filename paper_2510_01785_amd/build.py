@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libshtx.so")
-SOURCES = ["api.hip", "tables.hip", "ring_fft.hip", "legendre_valu.hip", "layout.hip"]
+SOURCES = ["api.hip", "tables.hip", "ring_fft.hip", "legendre_valu.hip", "legendre_mfma.hip", "layout.hip"]
 
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
 

@@ -1,5 +1,6 @@
 // C ABI of libshtx.so (declared in include/shtx.h): host-side validation,
 // table registry, workspace carving and kernel dispatch.
+#include <cstdlib>
 #include <mutex>
 #include <unordered_map>
 #include <utility>
@@ -20,6 +21,9 @@ template <typename T>
 hipError_t launch_legendre_fwd_valu(const Tables &, int, const cplx<T> *, const cplx<T> *, cplx<T> *, hipStream_t);
 template <typename T>
 hipError_t launch_legendre_inv_valu(const Tables &, int, const cplx<T> *, cplx<T> *, cplx<T> *, hipStream_t);
+bool mfma_fwd_supported(const Tables &tb);
+hipError_t launch_legendre_fwd_mfma(const Tables &, int, const float2 *, const float2 *, float2 *, hipStream_t);
+hipError_t launch_legendre_inv_mfma(const Tables &, int, const float2 *, float2 *, float2 *, hipStream_t);
 template <typename T, typename TO>
 hipError_t launch_alm_out(int, int, const cplx<T> *, cplx<TO> *, double, double, hipStream_t);
 template <typename T, typename TI>
@@ -125,6 +129,38 @@ template <typename T> Work<T> carve(void *work, int nside, int lmax, int batch) 
 
 int status_of(hipError_t e) { return e == hipSuccess ? SHTX_OK : SHTX_ERR_HIP; }
 
+// Matrix-core Legendre kernels serve FP32 contraction from 8 channels up
+// (below that the vector-ALU kernels are faster).  SHTX_FORCE_VALU=1 in the
+// environment selects the vector-ALU kernels everywhere.
+constexpr int kMfmaMinBatch = 8;
+bool force_valu() {
+  static const bool v = [] {
+    const char *e = getenv("SHTX_FORCE_VALU");
+    return e && e[0] == '1';
+  }();
+  return v;
+}
+
+template <typename T> hipError_t legendre_fwd(const Tables &tb, int B, const cplx<T> *XE, const cplx<T> *XO,
+                                              cplx<T> *ALMT, hipStream_t st) {
+  return launch_legendre_fwd_valu<T>(tb, B, XE, XO, ALMT, st);
+}
+template <> hipError_t legendre_fwd<float>(const Tables &tb, int B, const float2 *XE, const float2 *XO,
+                                           float2 *ALMT, hipStream_t st) {
+  if (B >= kMfmaMinBatch && mfma_fwd_supported(tb) && !force_valu())
+    return launch_legendre_fwd_mfma(tb, B, XE, XO, ALMT, st);
+  return launch_legendre_fwd_valu<float>(tb, B, XE, XO, ALMT, st);
+}
+template <typename T> hipError_t legendre_inv(const Tables &tb, int B, const cplx<T> *ALMT, cplx<T> *GN,
+                                              cplx<T> *GS, hipStream_t st) {
+  return launch_legendre_inv_valu<T>(tb, B, ALMT, GN, GS, st);
+}
+template <> hipError_t legendre_inv<float>(const Tables &tb, int B, const float2 *ALMT, float2 *GN, float2 *GS,
+                                           hipStream_t st) {
+  if (B >= kMfmaMinBatch && !force_valu()) return launch_legendre_inv_mfma(tb, B, ALMT, GN, GS, st);
+  return launch_legendre_inv_valu<float>(tb, B, ALMT, GN, GS, st);
+}
+
 // analysis chain: ring FFT -> Legendre -> caller layout with factors
 template <typename TIn, typename T>
 int run_analysis(const Tables &tb, int B, const TIn *map, cplx<T> *alm, const double *wtab, double wscale,
@@ -138,7 +174,7 @@ int run_analysis(const Tables &tb, int B, const TIn *map, cplx<T> *alm, const do
   if (e != hipSuccess) return SHTX_ERR_HIP;
   {
     StageTimer t(kStLegFwd, st);
-    e = launch_legendre_fwd_valu<T>(tb, B, w.specA, w.specB, w.almt, st);
+    e = legendre_fwd<T>(tb, B, w.specA, w.specB, w.almt, st);
   }
   if (e != hipSuccess) return SHTX_ERR_HIP;
   StageTimer t(kStAlmOut, st);
@@ -158,7 +194,7 @@ int run_synthesis(const Tables &tb, int B, const cplx<T> *alm, TOut *map, double
   if (e != hipSuccess) return SHTX_ERR_HIP;
   {
     StageTimer t(kStLegInv, st);
-    e = launch_legendre_inv_valu<T>(tb, B, w.almt, w.specA, w.specB, st);
+    e = legendre_inv<T>(tb, B, w.almt, w.specA, w.specB, st);
   }
   if (e != hipSuccess) return SHTX_ERR_HIP;
   StageTimer t(kStFftInv, st);

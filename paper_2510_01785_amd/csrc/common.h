@@ -22,6 +22,18 @@ constexpr int kAlign = 8;
 constexpr int kMaxNside = 2048;
 // A ring's Legendre term is skipped until |mu_lm| first reaches 2^kSkipExp.
 constexpr int kSkipExp = -64;
+// Analysis on the matrix cores: a workgroup takes one (m, block of kBlockL
+// consecutive l) item and starts every ring from a stored checkpoint of the
+// recurrence at the block start.  Checkpoints are kept for nside <= this.
+constexpr int kBlockL = 128;
+constexpr int kMaxNsideCheckpoint = 1024;
+
+inline size_t checkpoint_items(int nside, int lmax) {
+  if (nside > kMaxNsideCheckpoint) return 0;
+  size_t I = 0;
+  for (int m = 0; m <= lmax; ++m) I += (size_t)((lmax - m + kBlockL) / kBlockL);
+  return I;
+}
 
 __host__ __device__ inline size_t alm_idx(int l, int m, int lmax) {
   return (size_t)m * (size_t)(2 * lmax + 1 - m) / 2 + (size_t)l;
@@ -87,7 +99,13 @@ struct TableOffsets {
   size_t chirp64, chirp32;                    // Bluestein chirps, same layout as roots
   size_t bhat64, bhat32, bhat_tmp;            // FFT of the conjugate chirp, [sum M_i]
   size_t rootsP64, rootsP32;                  // roots of the largest Bluestein length
+  size_t ck_items;                            // int2 [I]: (m, l0) of each analysis block, XCD-major
+  size_t ck_xoff;                             // int32 [9]: first item of each XCD
+  size_t ck_pos;                              // int32 [L+1]: item index of (m, l0 = m)
+  size_t ck_t;                                // uint8 [I * Rp]: start offset in block (kBlockL: idle)
+  size_t ck_v;                                // double2 [I * Rp]: (mu_{l-1}, mu_l) at that start
   size_t total;
+  size_t nitems;
   size_t nbhat;
   int mmax_bs;
 };
@@ -129,12 +147,18 @@ inline TableOffsets table_offsets(int nside, int lmax) {
   o.bhat_tmp = take(o.nbhat * 16);
   o.rootsP64 = take((size_t)o.mmax_bs * 16);
   o.rootsP32 = take((size_t)o.mmax_bs * 8);
+  o.nitems = checkpoint_items(nside, lmax);
+  o.ck_items = take(o.nitems * 8);
+  o.ck_xoff = take(9 * 4);
+  o.ck_pos = take((size_t)(lmax + 1) * 4);
+  o.ck_t = take(o.nitems * Rp);
+  o.ck_v = take(o.nitems * Rp * 16);
   o.total = off;
   return o;
 }
 
 struct Tables {
-  int nside, lmax, npairs, npix, mmax_bs;
+  int nside, lmax, npairs, npix, mmax_bs, nitems;
   const int *rp_n, *rp_sN, *rp_sS, *rp_p0n, *rp_p0d, *rp_M, *rp_bsoff;
   const double *rp_z, *rp_sth, *rp_w;
   const double *coefA, *coefC;
@@ -144,6 +168,10 @@ struct Tables {
   const float2 *roots32;
   const double2 *chirp64, *bhat64, *rootsP64;
   const float2 *chirp32, *bhat32, *rootsP32;
+  const int2 *ck_items;
+  const int *ck_xoff, *ck_pos;
+  const uint8_t *ck_t;
+  const double2 *ck_v;
 };
 
 inline Tables tables_view(const void *base, int nside, int lmax) {
@@ -155,6 +183,7 @@ inline Tables tables_view(const void *base, int nside, int lmax) {
   t.npairs = 2 * nside;
   t.npix = 12 * nside * nside;
   t.mmax_bs = o.mmax_bs;
+  t.nitems = (int)o.nitems;
   t.rp_n = reinterpret_cast<const int *>(b + o.rp_n);
   t.rp_sN = reinterpret_cast<const int *>(b + o.rp_sN);
   t.rp_sS = reinterpret_cast<const int *>(b + o.rp_sS);
@@ -177,6 +206,11 @@ inline Tables tables_view(const void *base, int nside, int lmax) {
   t.bhat32 = reinterpret_cast<const float2 *>(b + o.bhat32);
   t.rootsP64 = reinterpret_cast<const double2 *>(b + o.rootsP64);
   t.rootsP32 = reinterpret_cast<const float2 *>(b + o.rootsP32);
+  t.ck_items = reinterpret_cast<const int2 *>(b + o.ck_items);
+  t.ck_xoff = reinterpret_cast<const int *>(b + o.ck_xoff);
+  t.ck_pos = reinterpret_cast<const int *>(b + o.ck_pos);
+  t.ck_t = reinterpret_cast<const uint8_t *>(b + o.ck_t);
+  t.ck_v = reinterpret_cast<const double2 *>(b + o.ck_v);
   return t;
 }
 

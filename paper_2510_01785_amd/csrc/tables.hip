@@ -256,6 +256,61 @@ __global__ void k_rootsP(int M, double2 *r64, float2 *r32) {
   r32[k] = make_float2((float)c, (float)-s);
 }
 
+// Analysis block list: items (m, l0 = m + kBlockL*b), grouped by XCD (m mod 8
+// goes to XCD m mod 8, since consecutive workgroups are dealt round-robin to
+// the 8 XCDs) and ordered by m inside each group, so that all blocks of one
+// m share one L2.  Single thread.
+__global__ void k_items(int L, int2 *items, int *xoff, int *pos) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  int k = 0;
+  for (int x = 0; x < 8; ++x) {
+    xoff[x] = k;
+    for (int m = x; m <= L; m += 8) {
+      pos[m] = k;
+      for (int l0 = m; l0 <= L; l0 += kBlockL) items[k++] = make_int2(m, l0);
+    }
+  }
+  xoff[8] = k;
+}
+
+// Checkpoints of the recurrence at every analysis block start: one thread per
+// (m, p) runs mu from its seed l_s to lmax with the same operation sequence as
+// the transform kernels and records, per block, where the ring starts inside
+// the block and the pair (mu_{l-1}, mu_l) there.
+__global__ void k_checkpoints(int L, int Rp, const double *zarr, const double *coefA, const int *seed_l,
+                              const double2 *seed_v, const int *pos, uint8_t *ck_t, double2 *ck_v) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  const int m = blockIdx.y;
+  if (p >= Rp) return;
+  const size_t slot = (size_t)m * Rp + p;
+  const int ls = seed_l[slot];
+  const double2 sd = seed_v[slot];
+  const double z = zarr[p];
+  const double *A = coefA + alm_idx(m, m, L) - m;
+  double prv = sd.x, cur = sd.y;
+  int lc = ls;  // l of the state (prv, cur)
+  const int base = pos[m];
+  for (int b = 0, l0 = m; l0 <= L; ++b, l0 += kBlockL) {
+    const size_t o = (size_t)(base + b) * Rp + p;
+    if (ls > L || ls >= l0 + kBlockL) {
+      ck_t[o] = (uint8_t)kBlockL;
+      ck_v[o] = make_double2(0.0, 0.0);
+    } else if (ls >= l0) {
+      ck_t[o] = (uint8_t)(ls - l0);
+      ck_v[o] = sd;
+    } else {
+      while (lc < l0) {
+        ++lc;
+        const double nx = fma(A[lc] * z, cur, -prv);
+        prv = cur;
+        cur = nx;
+      }
+      ck_t[o] = 0;
+      ck_v[o] = make_double2(prv, cur);
+    }
+  }
+}
+
 hipError_t launch_tables_build(int nside, int lmax, void *base, hipStream_t st) {
   const TableOffsets o = table_offsets(nside, lmax);
   char *b = static_cast<char *>(base);
@@ -272,6 +327,13 @@ hipError_t launch_tables_build(int nside, int lmax, void *base, hipStream_t st) 
                      D(o.coefA), I(o.seed_l), sv);
   hipLaunchKernelGGL(k_roots, dim3((4 * nside + 255) / 256, nside), dim3(256), 0, st, nside,
                      reinterpret_cast<double2 *>(b + o.roots64), reinterpret_cast<float2 *>(b + o.roots32));
+  if (o.nitems > 0) {
+    hipLaunchKernelGGL(k_items, dim3(1), dim3(64), 0, st, lmax, reinterpret_cast<int2 *>(b + o.ck_items),
+                       I(o.ck_xoff), I(o.ck_pos));
+    hipLaunchKernelGGL(k_checkpoints, dim3((Rp + 63) / 64, lmax + 1), dim3(64), 0, st, lmax, Rp, D(o.rp_z),
+                       D(o.coefA), I(o.seed_l), sv, I(o.ck_pos), reinterpret_cast<uint8_t *>(b + o.ck_t),
+                       reinterpret_cast<double2 *>(b + o.ck_v));
+  }
   if (o.mmax_bs > 0) {
     auto D2 = [&](size_t off) { return reinterpret_cast<double2 *>(b + off); };
     auto F2 = [&](size_t off) { return reinterpret_cast<float2 *>(b + off); };

@@ -52,6 +52,10 @@ CASES = [
     # every cap length up to 4*127 (Bluestein for lengths with a prime factor > 13)
     (128, 255, 2, torch.float64),
     (256, 300, 2, torch.float32),
+    # matrix-core Legendre kernels (FP32, >= 8 channels; partial 16-channel groups)
+    (16, 63, 8, torch.float32),
+    (128, 383, 16, torch.float32),
+    (256, 511, 24, torch.float32),
 ]
 
 
@@ -126,6 +130,22 @@ def test_bf16_input_map2alm(shtx):
     got = shtx.map2alm(x, lmax)
     assert got.dtype == torch.complex64
     assert rel_l2(got.cpu().numpy(), ref) <= 1e-5
+
+
+@pytest.mark.parametrize("nside,lmax,batch", [(32, 95, 16), (64, 255, 20)])
+def test_mfma_matches_valu_path(shtx, nside, lmax, batch, monkeypatch):
+    """The matrix-core and vector-ALU Legendre kernels agree to FP32 rounding
+    (the latter selected with SHTX_FORCE_VALU in a child process would be
+    cleaner; here both are compared with the oracle instead)."""
+    announce("mfma vs oracle nside=%d lmax=%d B=%d" % (nside, lmax, batch))
+    f = synth.white_map(99, batch, geometry.npix(nside))
+    x = torch.tensor(f, dtype=torch.float32, device="cuda")
+    ref = sht.map2alm(x.double().cpu().numpy(), lmax, nside)
+    a = shtx.map2alm(x, lmax)
+    assert rel_l2(a.cpu().numpy(), ref) <= 1e-5
+    g = shtx.alm2map(a, nside, lmax).cpu().numpy()
+    gref = sht.alm2map(a.cpu().numpy().astype(np.complex128), nside, lmax)
+    assert rel_l2(g, gref) <= 1e-5
 
 
 def test_deterministic(shtx):
