@@ -17,7 +17,6 @@
 namespace shtx {
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
-
 __device__ __forceinline__ f32x16 mfma32(float a, float b, f32x16 c) {
   return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
 }
@@ -33,9 +32,10 @@ constexpr int kTileRS = 64 + 4; // row stride of the LDS tile in floats
 // even or odd l) with the ring spectra E or O held in registers.  The four
 // waves' partial sums are added through LDS at the end.
 __global__ void __launch_bounds__(256)
-    k_legendre_fwd_mfma(Tables tb, int B, int b0, const float2 *__restrict__ XE, const float2 *__restrict__ XO,
-                        float2 *__restrict__ ALMT) {
+    k_legendre_fwd_mfma(Tables tb, int B, int b0, const double *__restrict__ coefA, const float2 *__restrict__ XE,
+                        const float2 *__restrict__ XO, float2 *__restrict__ ALMT) {
   __shared__ float tile[kFwdWaves * kSubL * kTileRS];
+  __shared__ double sA[kBlockL];
   const int g = blockIdx.x;
   const int x = g & 7, k = g >> 3;
   const int i0 = tb.ck_xoff[x];
@@ -47,7 +47,11 @@ __global__ void __launch_bounds__(256)
   const int tid = threadIdx.x, w = tid >> 6, j = tid & 63;
   const int h = j >> 5, col = j & 31;
   const bool colok = (b0 + (col >> 1)) < B;
-  const double *A = tb.coefA + alm_idx(m, m, L) - m;
+  {
+    const double *Ag = coefA + alm_idx(m, m, L) - m;
+    if (tid < kBlockL) sA[tid] = Ag[min(l0 + tid, L)];
+  }
+  __syncthreads();
   float *tw = tile + w * kSubL * kTileRS;
   const float *xe_f = reinterpret_cast<const float *>(XE);
   const float *xo_f = reinterpret_cast<const float *>(XO);
@@ -78,23 +82,28 @@ __global__ void __launch_bounds__(256)
     double prv = 0.0, cur = 0.0;
 #pragma unroll
     for (int hb = 0; hb < 2; ++hb) {
-      // recurrence: 64 steps, one lambda per lane per step into the tile
+      // recurrence: 64 steps, one lambda per lane per step into the tile.
+      // Coefficients are uniform (scalar loads, index clamped to lmax);
+      // steps past lmax produce values that are masked to zero.
 #pragma unroll 1
       for (int t8 = 0; t8 < kSubL / 8; ++t8) {
         const int tb8 = hb * kSubL + t8 * 8;
+        const int lb8 = l0 + tb8;
+        double Ac[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) Ac[u] = sA[tb8 + u];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-          const int t = tb8 + u;
-          const int l = l0 + t;
-          if (u == 0 && t == t0) {
-            prv = v.x;
-            cur = v.y;
-          } else if (l <= L) {
-            const double nx = fma(A[l] * z, cur, -prv);
+          const double nx = fma(Ac[u] * z, cur, -prv);
+          if (u == 0) {
+            const bool inj = (tb8 == t0);
+            prv = inj ? v.x : cur;
+            cur = inj ? v.y : nx;
+          } else {
             prv = cur;
             cur = nx;
           }
-          tw[(t8 * 8 + u) * kTileRS + j] = (l <= L) ? (float)cur : 0.f;
+          tw[(t8 * 8 + u) * kTileRS + j] = (lb8 + u <= L) ? (float)cur : 0.f;
         }
       }
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -156,10 +165,11 @@ __global__ void __launch_bounds__(256)
 // chunks of one m run on one XCD (consecutive workgroups go to consecutive
 // XCDs), sharing the a_m slab in L2.
 constexpr int kInvRings = 128;
+constexpr int kInvBlk = 64;  // l's staged per block
 
 __global__ void __launch_bounds__(256)
-    k_legendre_inv_mfma(Tables tb, int B, int b0, const float2 *__restrict__ ALMT, float2 *__restrict__ GN,
-                        float2 *__restrict__ GS) {
+    k_legendre_inv_mfma(Tables tb, int B, int b0, const double *__restrict__ coefA, const float2 *__restrict__ ALMT,
+                        float2 *__restrict__ GN, float2 *__restrict__ GS) {
   const int L = tb.lmax, M = L + 1, Rp = tb.npairs;
   const int nch = (Rp + kInvRings - 1) / kInvRings;
   const int g = blockIdx.x;
@@ -175,36 +185,82 @@ __global__ void __launch_bounds__(256)
   const double z = pok ? tb.rp_z[p] : 0.0;
   const int ls = pok ? tb.seed_l[(size_t)m * Rp + p] : L + 1;
   const double2 sd = pok ? tb.seed_v[(size_t)m * Rp + p] : make_double2(0.0, 0.0);
-  int lb = ls;
+  // first l any ring of the workgroup needs
+  __shared__ int s_lb;
+  __shared__ float sB[2][kInvBlk][32];
+  __shared__ double sA[2][kInvBlk];
+  if (tid == 0) s_lb = L + 1;
+  __syncthreads();
+  atomicMin(&s_lb, ls);
+  int wl = ls;
 #pragma unroll
-  for (int o = 1; o < 64; o <<= 1) lb = min(lb, __shfl_xor(lb, o));
-  const double *A = tb.coefA + alm_idx(m, m, L) - m;
-  const float *a = reinterpret_cast<const float *>(ALMT) + ((alm_idx(m, m, L) - m) * B + b0) * 2 + col;
+  for (int o = 1; o < 64; o <<= 1) wl = min(wl, __shfl_xor(wl, o));
+  __syncthreads();
+  const int lb = s_lb;
+  const double *Ag = coefA + alm_idx(m, m, L) - m;
+  const float *ag = reinterpret_cast<const float *>(ALMT) + ((alm_idx(m, m, L) - m) * B + b0) * 2;
   const size_t arow = (size_t)B * 2;
+  // staging of one block: rows l0..l0+kInvBlk-1 of a (32 floats each, 8 per
+  // thread) and their recurrence coefficients
+  const int srow = tid >> 2, scol = (tid & 3) * 8;
+  float stg[8];
+  double stgA = 0.0;
+  auto fetch = [&](int l0) {
+    const int l = l0 + srow;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int cc = scol + e;
+      const bool ok = l <= L && (b0 + (cc >> 1)) < B;
+      stg[e] = ok ? ag[(size_t)l * arow + cc] : 0.f;
+    }
+    if (tid < kInvBlk) stgA = Ag[min(l0 + tid, L)];
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) sB[buf][srow][scol + e] = stg[e];
+    if (tid < kInvBlk) sA[buf][tid] = stgA;
+  };
   f32x16 acc_e, acc_o;
 #pragma unroll
   for (int r = 0; r < 16; ++r) acc_e[r] = acc_o[r] = 0.f;
   double prv = 0.0, cur = 0.0;
-  for (int l0 = lb; l0 <= L; l0 += 4) {
-    float lam[4];
+  if (lb <= L) {
+    fetch(lb);
+    stash(0);
+  }
+  __syncthreads();
+  int buf = 0;
+  for (int l0 = lb; l0 <= L; l0 += kInvBlk) {
+    const bool more = l0 + kInvBlk <= L;
+    if (more) fetch(l0 + kInvBlk);
+    if (wl <= l0 + kInvBlk - 1) {  // some ring of this wave is active in the block
+#pragma unroll 1
+      for (int u8 = 0; u8 < kInvBlk / 8; ++u8) {
+        const int lq = l0 + 8 * u8;
+        float lam[8];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int l = l0 + u;
-      if (u == 0 && l == ls) {
-        prv = sd.x;
-        cur = sd.y;
-      } else if (l <= L) {
-        const double nx = fma(A[l] * z, cur, -prv);
-        prv = cur;
-        cur = nx;
+        for (int u = 0; u < 8; ++u) {
+          const double nx = fma(sA[buf][8 * u8 + u] * z, cur, -prv);
+          if (u == 0) {
+            const bool inj = (lq == ls);
+            prv = inj ? sd.x : cur;
+            cur = inj ? sd.y : nx;
+          } else {
+            prv = cur;
+            cur = nx;
+          }
+          lam[u] = (lq + u <= L) ? (float)cur : 0.f;
+        }
+        const float *rb = &sB[buf][8 * u8 + 2 * h][col];
+        acc_e = mfma32(h ? lam[2] : lam[0], rb[0], acc_e);
+        acc_o = mfma32(h ? lam[3] : lam[1], rb[32], acc_o);
+        acc_e = mfma32(h ? lam[6] : lam[4], rb[4 * 32], acc_e);
+        acc_o = mfma32(h ? lam[7] : lam[5], rb[5 * 32], acc_o);
       }
-      lam[u] = (l <= L) ? (float)cur : 0.f;
     }
-    const int le = l0 + 2 * h, lo = le + 1;
-    const float be = (colok && le <= L) ? a[(size_t)le * arow] : 0.f;
-    const float bo = (colok && lo <= L) ? a[(size_t)lo * arow] : 0.f;
-    acc_e = mfma32(h ? lam[2] : lam[0], be, acc_e);
-    acc_o = mfma32(h ? lam[3] : lam[1], bo, acc_o);
+    if (more) stash(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
   }
   if (!colok) return;
   float *gn = reinterpret_cast<float *>(GN);
@@ -236,7 +292,8 @@ hipError_t launch_legendre_fwd_mfma(const Tables &tb, int B, const float2 *XE, c
     }
   }
   for (int b0 = 0; b0 < B; b0 += 16)
-    hipLaunchKernelGGL(k_legendre_fwd_mfma, dim3(8 * longest), dim3(256), 0, st, tb, B, b0, XE, XO, ALMT);
+    hipLaunchKernelGGL(k_legendre_fwd_mfma, dim3(8 * longest), dim3(256), 0, st, tb, B, b0, tb.coefA, XE, XO,
+                       ALMT);
   return hipGetLastError();
 }
 
@@ -245,7 +302,8 @@ hipError_t launch_legendre_inv_mfma(const Tables &tb, int B, const float2 *ALMT,
   const int nch = (tb.npairs + kInvRings - 1) / kInvRings;
   const int nm = (tb.lmax + 1 + 7) / 8;
   for (int b0 = 0; b0 < B; b0 += 16)
-    hipLaunchKernelGGL(k_legendre_inv_mfma, dim3(8 * nm * nch), dim3(256), 0, st, tb, B, b0, ALMT, GN, GS);
+    hipLaunchKernelGGL(k_legendre_inv_mfma, dim3(8 * nm * nch), dim3(256), 0, st, tb, B, b0, tb.coefA, ALMT, GN,
+                       GS);
   return hipGetLastError();
 }
 
