@@ -10,8 +10,10 @@ dominant kernel (timed with HIP events recorded on the transform's stream
 inside the timed region) and the FP64 CPU oracle's rate on a bounded sample.
 """
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -43,6 +45,38 @@ def parse():
                     help="only run a plain device copy of this many MiB (5 times), "
                          "to calibrate HBM byte counters, and exit")
     return ap.parse_args()
+
+
+STAGE_KERNEL = {  # stage -> (kernel symbol, source file)
+    "ring_fft_fwd": ("k_ring_fft_fwd", "ring_fft.hip"),
+    "legendre_fwd": ("k_legendre_fwd_mfma", "legendre_mfma.hip"),
+    "alm_out": ("k_alm_out", "layout.hip"),
+    "alm_in": ("k_alm_in", "layout.hip"),
+    "legendre_inv": ("k_legendre_inv_mfma", "legendre_mfma.hip"),
+    "ring_fft_inv": ("k_ring_fft_inv", "ring_fft.hip"),
+}
+
+
+def source_sha(fname):
+    path = os.path.join(ROOT, "paper_2510_01785_amd", "csrc", fname)
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(kernel, fname, workload):
+    """HBM bytes per dispatch of `kernel` from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE, calibrated on a plain copy), or None when the
+    summary is missing or the kernel source changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_%s.txt" % workload)
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        text = f.read()
+    m = re.search(r"^%s\s+source=(\w+)\s+fetch_bytes=([0-9.e+]+)\s+write_bytes=([0-9.e+]+)" % kernel,
+                  text, re.M)
+    if not m or m.group(1) != source_sha(fname):
+        return None
+    return float(m.group(2)) + float(m.group(3))
 
 
 def triples(nside, lmax):
@@ -140,10 +174,12 @@ def main():
     npix = 12 * nside * nside
     spec_bytes = 2 * (lmax + 1) * 2 * nside * B * csize
     alm_bytes = (lmax + 1) * (lmax + 2) // 2 * B * csize
+    mfma = args.dtype in ("f32", "bf16") and B >= 8
+    leg_bound = "mfma" if mfma else "alu"
     work = {
         # algorithmic work per call of each stage
-        "legendre_fwd": ("alu", 4.0 * tr * B, "TFLOP/s"),
-        "legendre_inv": ("alu", 4.0 * tr * B, "TFLOP/s"),
+        "legendre_fwd": (leg_bound, 4.0 * tr * B, "TFLOP/s"),
+        "legendre_inv": (leg_bound, 4.0 * tr * B, "TFLOP/s"),
         "ring_fft_fwd": ("hbm", float(npix * B * esize + spec_bytes), "GB/s"),
         "ring_fft_inv": ("hbm", float(npix * B * esize + spec_bytes), "GB/s"),
         "alm_out": ("hbm", 2.0 * alm_bytes, "GB/s"),
@@ -153,12 +189,19 @@ def main():
     sec = stages[dom]["ms_per_call"] / 1000.0
     if unit == "TFLOP/s":
         achieved = amount / sec / 1e12
-        peak = PEAK["fp64_vector_TFs"] if args.dtype == "f64" else PEAK["fp32_vector_TFs"]
+        if bound == "mfma":
+            peak = PEAK["fp32_mfma_TFs"]
+        else:
+            peak = PEAK["fp64_vector_TFs"] if args.dtype == "f64" else PEAK["fp32_vector_TFs"]
     else:
         achieved = amount / sec / 1e9
         peak = PEAK["hbm_GBs"]
-    roof = dict(kernel=dom, bound=bound, achieved=round(achieved, 3), peak=peak, unit=unit,
-                frac=round(achieved / peak, 4), traffic=None)
+    workload = "nside%d_lmax%d_b%d_%s" % (nside, lmax, B, args.dtype)
+    kname, kfile = STAGE_KERNEL[dom]
+    traffic = measured_traffic(kname, kfile, workload) if (mfma or unit != "TFLOP/s") else None
+    roof = dict(kernel=kname, bound=bound, achieved=round(achieved, 3), peak=peak, unit=unit,
+                frac=round(achieved / peak, 4), traffic=traffic,
+                algorithmic=amount, per="launch" if B <= 16 else "call")
     out = {
         "metric": "SHT fwd+inv maps/s at Nside=1024 lmax=2047 B=16; % roofline; p50/p99 latency",
         "value": round(value, 3),
