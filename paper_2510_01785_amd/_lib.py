@@ -9,7 +9,7 @@ F64, F32, BF16 = 0, 1, 2
 OK, ERR_ARG, ERR_UNSUPPORTED, ERR_WORKSPACE, ERR_HIP, ERR_TABLES = range(6)
 
 EXPORTS = ("shtx_version", "shtx_status_string", "shtx_tables_bytes", "shtx_tables_build",
-           "shtx_tables_release", "shtx_workspace_bytes", "shtx_map2alm", "shtx_alm2map",
+           "shtx_tables_release", "shtx_tables_work", "shtx_workspace_bytes", "shtx_map2alm", "shtx_alm2map",
            "shtx_map2alm_backward", "shtx_alm2map_backward", "shtx_profile_enable",
            "shtx_profile_reset", "shtx_profile_read", "shtx_stage_name")
 STAGES = ("ring_fft_fwd", "legendre_fwd", "alm_out", "alm_in", "legendre_inv", "ring_fft_inv")
@@ -44,6 +44,8 @@ def lib():
     L.shtx_tables_build.restype = i
     L.shtx_tables_release.argtypes = [vp]
     L.shtx_tables_release.restype = i
+    L.shtx_tables_work.argtypes = [vp, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_longlong), vp]
+    L.shtx_tables_work.restype = i
     L.shtx_workspace_bytes.argtypes = [i, i, i, i]
     L.shtx_workspace_bytes.restype = sz
     for name in ("shtx_map2alm", "shtx_alm2map", "shtx_map2alm_backward", "shtx_alm2map_backward"):

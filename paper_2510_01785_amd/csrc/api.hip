@@ -1,5 +1,6 @@
 // C ABI of libshtx.so (declared in include/shtx.h): host-side validation,
 // table registry, workspace carving and kernel dispatch.
+#include <algorithm>
 #include <cstdlib>
 #include <mutex>
 #include <unordered_map>
@@ -266,6 +267,27 @@ int shtx_tables_build(int nside, int lmax, void *tables, size_t tables_bytes, vo
   if (e != hipSuccess) return SHTX_ERR_HIP;
   std::lock_guard<std::mutex> lk(g_mu);
   g_tables[tables] = Registered{nside, lmax, tables_view(tables, nside, lmax)};
+  return SHTX_OK;
+}
+
+int shtx_tables_work(const void *tables, long long *executed, long long *full, void *stream) {
+  if (!executed || !full) return SHTX_ERR_ARG;
+  Registered r;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_tables.find(tables);
+    if (it == g_tables.end()) return SHTX_ERR_TABLES;
+    r = it->second;
+  }
+  const int L = r.lmax, Rp = 2 * r.nside;
+  std::vector<int> ls((size_t)(L + 1) * Rp);
+  hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
+  if (e == hipSuccess) e = hipMemcpy(ls.data(), r.view.seed_l, ls.size() * sizeof(int), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return SHTX_ERR_HIP;
+  long long s = 0;
+  for (int v : ls) s += (long long)(L + 1 - std::min(v, L + 1));
+  *executed = s;
+  *full = (long long)nalm_of(L) * Rp;
   return SHTX_OK;
 }
 

@@ -57,6 +57,17 @@ def get_tables(nside, lmax, device):
         return t
 
 
+def tables_work(nside, lmax, device):
+    """(executed, full) Legendre triples of the pruned and the full (l, m,
+    ring pair) triangle for the tables of (nside, lmax) on `device`."""
+    import ctypes
+    t = get_tables(nside, lmax, device)
+    ex, fu = ctypes.c_longlong(0), ctypes.c_longlong(0)
+    _lib.check("shtx_tables_work", _lib.lib().shtx_tables_work(t.data_ptr(), ctypes.byref(ex), ctypes.byref(fu),
+                                                               _stream_ptr(torch.device(device))))
+    return ex.value, fu.value
+
+
 def clear_tables():
     with _tables_lock:
         L = _lib.lib()
