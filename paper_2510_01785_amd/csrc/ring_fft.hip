@@ -22,43 +22,33 @@ namespace shtx {
 
 constexpr int kFftOutMax = 16;  // complex values per thread per stage
 
-// LDS index of logical element o of the FFT work buffer: one padding slot
-// every 16 elements, so that the stride-R writes of a Stockham stage (thread
-// i writing elements R i + q) fall into different banks.
-__device__ __forceinline__ int lp_idx(int o) { return o + (o >> 4); }
+// Index of logical element o in the LDS work buffer.  Transforms of length
+// >= 256 insert one padding slot every 16 elements, so that the stride-R
+// writes of a Stockham stage fall into different banks; with that rule a
+// channel of length n occupies n + n/16 slots and element o + r*s sits at
+// lidx(o) + r*(s + s/16) for any stride s that is a multiple of 16, so every
+// stage addresses its R values from one base with a constant stride.
+__device__ __forceinline__ int lidx(int o, int pad) { return pad ? o + (o >> 4) : o; }
+__device__ __forceinline__ int lstride(int s, int pad) { return pad ? s + (s >> 4) : s; }
 inline size_t lds_elems(size_t n) { return n + (n >> 4) + 1; }
+constexpr int kPadMin = 256;  // transform length from which the buffer is padded
 
-// Twiddles of power-of-two transforms of length N come from an octant table
-// in LDS, tq[r] = exp(-2 pi i r / N) for r = 0..N/8: for e = q N/4 + r,
-// w^e = (-i)^q w^r, and for r > N/8, w^r = (sin phi, -cos phi) with
-// (cos phi, -sin phi) = tq[N/4 - r].
-template <typename C>
-__device__ __forceinline__ C tw_quarter(const C *tq, int e, int lq /* log2(N/4) */) {
+// w^e = exp(-2 pi i e / N) for 0 <= e < N from an octant table in LDS,
+// tq[r] = w^r for r = 0..N/8 (N = 4 << lq): with e = q N/4 + r,
+// w^e = (-i)^q w^r, and for r > N/8, w^r = (sin phi, -cos phi) where
+// (cos phi, -sin phi) = tq[N/4 - r].  Branch-free: selects and sign flips.
+template <typename C> __device__ __forceinline__ C tw_oct(const C *tq, int e, int lq) {
+  const int Q = 1 << lq;
   const int q = e >> lq;
-  const int r = e - (q << lq);
-  const int h = (1 << lq) >> 1;
-  C w;
-  if (r <= h) {
-    w = tq[r];
-  } else {
-    const C v = tq[(1 << lq) - r];
-    w = cmk<C>(-v.y, -v.x);
-  }
-  switch (q & 3) {
-    case 0: return w;
-    case 1: return cmk<C>(w.y, -w.x);
-    case 2: return cmk<C>(-w.x, -w.y);
-    default: return cmk<C>(-w.y, w.x);
-  }
+  const int r = e & (Q - 1);
+  const bool hi = r > (Q >> 1);
+  const C v = tq[hi ? Q - r : r];
+  const auto x0 = hi ? -v.y : v.x;
+  const auto y0 = hi ? -v.x : v.y;
+  const auto a = (q & 1) ? y0 : x0;
+  const auto b = (q & 1) ? x0 : y0;
+  return cmk<C>((q & 2) ? -a : a, ((q + 1) & 2) ? -b : b);
 }
-
-// Root access of one stage: either a full table in global memory (any n)
-// or an octant table in LDS (power-of-two n).
-template <typename C> struct Roots {
-  const C *tab;
-  int lq;  // >= 0: octant table in LDS for length 4 << lq; < 0: full table
-  __device__ __forceinline__ C operator()(int e) const { return lq >= 0 ? tw_quarter(tab, e, lq) : tab[e]; }
-};
 
 // In-register DFTs of 2, 4, 8 and 16 points (forward, exp(-2 pi i/R)).
 template <typename C> __device__ __forceinline__ C mul_mi(C a) { return cmk<C>(a.y, -a.x); }  // * (-i)
@@ -153,6 +143,45 @@ template <typename C, int R> __device__ __forceinline__ void dftR(C (&u)[R]) {
   else dft2(u[0], u[1]);
 }
 
+// u[r] *= w^{r e} for r = 1..R-1 (e < N/R, so no exponent wraps).  Radix 16
+// takes w^e, w^2e, w^3e, w^4e, w^8e, w^12e from the table and forms the other
+// nine as one product each; radix 8 forms w^5e..w^7e from w^4e.
+template <typename C, int R> __device__ __forceinline__ void twiddle(C (&u)[R], const C *tq, int e, int lq) {
+  if constexpr (R == 2) {
+    u[1] = cmul(u[1], tw_oct(tq, e, lq));
+  } else if constexpr (R == 4) {
+    u[1] = cmul(u[1], tw_oct(tq, e, lq));
+    u[2] = cmul(u[2], tw_oct(tq, 2 * e, lq));
+    u[3] = cmul(u[3], tw_oct(tq, 3 * e, lq));
+  } else if constexpr (R == 8) {
+    const C w1 = tw_oct(tq, e, lq), w2 = tw_oct(tq, 2 * e, lq), w3 = tw_oct(tq, 3 * e, lq);
+    const C w4 = tw_oct(tq, 4 * e, lq);
+    u[1] = cmul(u[1], w1);
+    u[2] = cmul(u[2], w2);
+    u[3] = cmul(u[3], w3);
+    u[4] = cmul(u[4], w4);
+    u[5] = cmul(u[5], cmul(w4, w1));
+    u[6] = cmul(u[6], cmul(w4, w2));
+    u[7] = cmul(u[7], cmul(w4, w3));
+  } else {
+    C lo[4], hi[4];
+    lo[1] = tw_oct(tq, e, lq);
+    lo[2] = tw_oct(tq, 2 * e, lq);
+    lo[3] = tw_oct(tq, 3 * e, lq);
+    hi[1] = tw_oct(tq, 4 * e, lq);
+    hi[2] = tw_oct(tq, 8 * e, lq);
+    hi[3] = tw_oct(tq, 12 * e, lq);
+#pragma unroll
+    for (int r1 = 1; r1 < 4; ++r1) u[r1] = cmul(u[r1], lo[r1]);
+#pragma unroll
+    for (int r2 = 1; r2 < 4; ++r2) {
+      u[4 * r2] = cmul(u[4 * r2], hi[r2]);
+#pragma unroll
+      for (int r1 = 1; r1 < 4; ++r1) u[4 * r2 + r1] = cmul(u[4 * r2 + r1], cmul(hi[r2], lo[r1]));
+    }
+  }
+}
+
 // Optional fused operations on the first stage's inputs / last stage's
 // outputs of a power-of-two transform (Bluestein chirp products).
 enum FuseIn { kInPlain = 0, kInChirp = 1 };        // x_j * c_j for j < nvalid, 0 beyond
@@ -165,37 +194,129 @@ template <typename T> struct Fuse {
   T scale;
 };
 
-// Stockham stage of power-of-two radix R on G channels of length n (span p):
-// butterfly i of channel c reads x[i + r n/R], twiddles by w^{r k n/(R p)}
-// (k = i mod p), and writes y[R(i-k) + k + q p].  All inputs are read into
-// registers before the workgroup barrier, so the buffer is updated in place.
-template <typename T, int NT, int R, int fin, int fout>
-__device__ __noinline__ void stage_pow2(cplx<T> *buf, int n, int G, int p, int lp, Roots<cplx<T>> roots,
-                                        Fuse<T> fz) {
+// Stockham stage of power-of-two radix R on G channels of length n = 2^logn
+// with span p = 2^logp: butterfly i of channel c reads x[i + r n/R], twiddles
+// by w^{r k n/(R p)} (k = i mod p) and writes y[R(i-k) + k + q p].  The first
+// stage (p = 1) has no twiddles.  All inputs are read into registers before
+// the workgroup barrier, so the buffer is updated in place.  Every index is a
+// shift or a mask; the R values of a butterfly sit at a constant LDS stride
+// from one base (padding rule of lidx).  fin / fout select the fused
+// operations (uniform across the workgroup).
+template <typename T, int NT, int R>
+__device__ __forceinline__ void stage_p2(cplx<T> *buf, int logn, int G, int logp, int pad, const cplx<T> *tq,
+                                         const Fuse<T> &fz, int fin, int fout) {
+  using C = cplx<T>;
+  constexpr int LR = R == 16 ? 4 : R == 8 ? 3 : R == 4 ? 2 : 1;
+  constexpr int NB = kFftOutMax / R;
+  const int n = 1 << logn;
+  const int lq = logn - 2;
+  const int logTq = logn - LR;
+  const int Tq = 1 << logTq;
+  const int nb = G << logTq;
+  const int p = 1 << logp;
+  const int cs = lstride(n, pad);
+  const int is = lstride(Tq, pad);
+  const int os = logp == 0 ? 1 : lstride(p, pad);
+  // Opaque copy of the thread index: keeps the per-butterfly index arithmetic
+  // inside the stage (hoisted out of the stage loop it would stay live over
+  // the whole transform and spill).
+  int tid = threadIdx.x;
+  asm volatile("" : "+v"(tid));
+  C v[NB][R];
+#pragma unroll
+  for (int s = 0; s < NB; ++s) {
+    const int b = tid + s * NT;
+    if (b < nb) {
+      const int c = b >> logTq, i = b & (Tq - 1);
+      const int ib = c * cs + lidx(i, pad);
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[s][r] = buf[ib + r * is];
+      if (fin == kInChirp) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const int j = i + r * Tq;
+          v[s][r] = (j < fz.nvalid) ? cmul(v[s][r], fz.chirp[j]) : cmk<C>(0, 0);
+        }
+      }
+      if (logp > 0) twiddle<C, R>(v[s], tq, (i & (p - 1)) << (logTq - logp), lq);
+      dftR<C, R>(v[s]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int s = 0; s < NB; ++s) {
+    const int b = tid + s * NT;
+    if (b < nb) {
+      const int c = b >> logTq, i = b & (Tq - 1);
+      const int k = i & (p - 1);
+      const int o0 = ((i - k) << LR) + k;
+      const int ob = c * cs + lidx(o0, pad);
+      if (fout == kOutPlain) {
+#pragma unroll
+        for (int q = 0; q < R; ++q) buf[ob + q * os] = v[s][q];
+      } else if (fout == kOutBhat) {
+#pragma unroll
+        for (int q = 0; q < R; ++q) buf[ob + q * os] = cconj(cmul(v[s][q], fz.bhat[o0 + q * p]));
+      } else {
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+          const int o = o0 + q * p;
+          const C cv = cconj(v[s][q]);
+          if (o < fz.nvalid) buf[ob + q * os] = cmul(fz.chirp[o], cmk<C>(cv.x * fz.scale, cv.y * fz.scale));
+        }
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// Stockham FFT of G channels of power-of-two length n = 2^logn in LDS:
+// radix-16 stages, then one radix 2/4/8 stage for the remaining factor (or a
+// single radix-4/8 stage for n = 4, 8); twiddles from the LDS octant table tq
+// of length n; fused input operation fin on the first stage and output
+// operation fout on the last.
+template <typename T, int NT>
+__device__ __forceinline__ void fft_p2(cplx<T> *buf, int logn, int G, int pad, const cplx<T> *tq, const Fuse<T> &fz,
+                                       int fin, int fout) {
+  const int n16 = logn >> 2, rem = logn & 3;
+  int logp = 0;
+#pragma unroll 1
+  for (int st = 0; st < n16; ++st, logp += 4) {
+    const int fi = st == 0 ? fin : kInPlain;
+    const int fo = (st == n16 - 1 && rem == 0) ? fout : kOutPlain;
+    stage_p2<T, NT, 16>(buf, logn, G, logp, pad, tq, fz, fi, fo);
+  }
+  const int fi = n16 == 0 ? fin : kInPlain;
+  if (rem == 1) stage_p2<T, NT, 2>(buf, logn, G, logp, pad, tq, fz, fi, fout);
+  else if (rem == 2) stage_p2<T, NT, 4>(buf, logn, G, logp, pad, tq, fz, fi, fout);
+  else if (rem == 3) stage_p2<T, NT, 8>(buf, logn, G, logp, pad, tq, fz, fi, fout);
+}
+
+// Mixed-radix stages for ring lengths n = 4i with odd factors <= 13 (short
+// polar rings): twiddles from the ring's full root table in global memory.
+// Radix-4/2 stage (span p):
+template <typename T, int NT, int R>
+__device__ __forceinline__ void stage_mix_p2(cplx<T> *buf, int n, int G, int p, int pad,
+                                             const cplx<T> *__restrict__ roots) {
   using C = cplx<T>;
   constexpr int NB = kFftOutMax / R;
   const int Tq = n / R;
   const int nb = G * Tq;
-  const int step = n >> (lp + __builtin_ctz(R));
+  const int step = n / (R * p);
+  int tid = threadIdx.x;
+  asm volatile("" : "+v"(tid));
   C v[NB][R];
 #pragma unroll
   for (int s = 0; s < NB; ++s) {
-    const int b = threadIdx.x + s * NT;
+    const int b = tid + s * NT;
     if (b < nb) {
       const int c = b / Tq, i = b - c * Tq;
-      const int k = i & (p - 1);
-      const int xb = c * n + i;
+      const int k = i % p;
       const int e = k * step;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        C u;
-        if constexpr (fin == kInChirp) {
-          const int j = i + r * Tq;
-          u = (j < fz.nvalid) ? cmul(buf[lp_idx(xb + r * Tq)], fz.chirp[j]) : cmk<C>(0, 0);
-        } else {
-          u = buf[lp_idx(xb + r * Tq)];
-        }
-        v[s][r] = (r == 0) ? u : cmul(u, roots(r * e));
+        const C u = buf[lidx(c * n + i + r * Tq, pad)];
+        v[s][r] = (r == 0) ? u : cmul(u, roots[r * e]);
       }
       dftR<C, R>(v[s]);
     }
@@ -203,25 +324,13 @@ __device__ __noinline__ void stage_pow2(cplx<T> *buf, int n, int G, int p, int l
   __syncthreads();
 #pragma unroll
   for (int s = 0; s < NB; ++s) {
-    const int b = threadIdx.x + s * NT;
+    const int b = tid + s * NT;
     if (b < nb) {
       const int c = b / Tq, i = b - c * Tq;
-      const int k = i & (p - 1);
+      const int k = i % p;
       const int o0 = (i - k) * R + k;
-      const int yb = c * n + o0;
 #pragma unroll
-      for (int q = 0; q < R; ++q) {
-        C val = v[s][q];
-        const int o = o0 + q * p;
-        if constexpr (fout == kOutBhat) {
-          val = cconj(cmul(val, fz.bhat[o]));
-        } else if constexpr (fout == kOutChirp) {
-          if (o >= fz.nvalid) continue;
-          const C cv = cconj(val);
-          val = cmul(fz.chirp[o], cmk<C>(cv.x * fz.scale, cv.y * fz.scale));
-        }
-        buf[lp_idx(yb + q * p)] = val;
-      }
+      for (int q = 0; q < R; ++q) buf[lidx(c * n + o0 + q * p, pad)] = v[s][q];
     }
   }
   __syncthreads();
@@ -229,19 +338,20 @@ __device__ __noinline__ void stage_pow2(cplx<T> *buf, int n, int G, int p, int l
 
 // Stage of odd radix R (span p): thread per output,
 //   y[g pR + q p + k] = sum_r x[g p + k + r n/R] w^{r (n/(pR)) (k + q p)}.
-// Used for R <= kMaxDirectPrime only.
 template <typename T, int NT>
-__device__ __noinline__ void stage_odd(cplx<T> *buf, int n, int G, int p, int R,
-                                       const cplx<T> *__restrict__ roots) {
+__device__ __forceinline__ void stage_odd(cplx<T> *buf, int n, int G, int p, int R, int pad,
+                                          const cplx<T> *__restrict__ roots) {
   using C = cplx<T>;
   const int tot = G * n;
   const int Tn = n / R;
   const int pR = p * R;
   const int step = n / pR;
+  int tid = threadIdx.x;
+  asm volatile("" : "+v"(tid));
   C out[kFftOutMax];
 #pragma unroll
   for (int s = 0; s < kFftOutMax; ++s) {
-    const int o = threadIdx.x + s * NT;
+    const int o = tid + s * NT;
     if (o < tot) {
       const int c = o / n;
       const int oo = o - c * n;
@@ -251,10 +361,10 @@ __device__ __noinline__ void stage_odd(cplx<T> *buf, int n, int G, int p, int R,
       const int k = rr - q * p;
       const int xb = c * n + g * p + k;
       const int be = step * (k + q * p);
-      C acc = buf[lp_idx(xb)];
+      C acc = buf[lidx(xb, pad)];
       int e = be;
       for (int r = 1; r < R; ++r) {
-        acc = cadd(acc, cmul(buf[lp_idx(xb + r * Tn)], roots[e]));
+        acc = cadd(acc, cmul(buf[lidx(xb + r * Tn, pad)], roots[e]));
         e += be;
         if (e >= n) e -= n;
       }
@@ -264,76 +374,26 @@ __device__ __noinline__ void stage_odd(cplx<T> *buf, int n, int G, int p, int R,
   __syncthreads();
 #pragma unroll
   for (int s = 0; s < kFftOutMax; ++s) {
-    const int o = threadIdx.x + s * NT;
-    if (o < tot) buf[lp_idx(o)] = out[s];
+    const int o = tid + s * NT;
+    if (o < tot) buf[lidx(o, pad)] = out[s];
   }
   __syncthreads();
-}
-
-// Stockham FFT of G channels of power-of-two length n (radix 16 stages and
-// one radix 2/4/8 stage), twiddles from the LDS octant table tq; optional
-// fused first-stage input and last-stage output operations.
-template <typename T, int NT, int R>
-__device__ __forceinline__ void stage_pow2_any(cplx<T> *buf, int n, int G, int p, int lp, Roots<cplx<T>> roots,
-                                               int fin, int fout, const Fuse<T> &fz) {
-  if (fin == kInChirp) {
-    if (fout == kOutBhat) stage_pow2<T, NT, R, kInChirp, kOutBhat>(buf, n, G, p, lp, roots, fz);
-    else stage_pow2<T, NT, R, kInChirp, kOutPlain>(buf, n, G, p, lp, roots, fz);
-  } else if (fout == kOutBhat) {
-    stage_pow2<T, NT, R, kInPlain, kOutBhat>(buf, n, G, p, lp, roots, fz);
-  } else if (fout == kOutChirp) {
-    stage_pow2<T, NT, R, kInPlain, kOutChirp>(buf, n, G, p, lp, roots, fz);
-  } else {
-    stage_pow2<T, NT, R, kInPlain, kOutPlain>(buf, n, G, p, lp, roots, fz);
-  }
-}
-
-template <typename T, int NT>
-__device__ __noinline__ void fft_pow2(cplx<T> *buf, int n, int G, const cplx<T> *tq, int fin, int fout,
-                                      Fuse<T> fz) {
-  const Roots<cplx<T>> roots{tq, __builtin_ctz(n) - 2};
-  const int e2 = __builtin_ctz(n);
-  const int nst = e2 / 4 + ((e2 & 3) ? 1 : 0);
-  int p = 1, lp = 0, st = 0;
-  // the remainder radix first
-  const int rr = e2 & 3;
-  if (rr) {
-    const int fo = (st == nst - 1) ? fout : kOutPlain;
-    if (rr == 1) stage_pow2_any<T, NT, 2>(buf, n, G, p, lp, roots, fin, fo, fz);
-    else if (rr == 2) stage_pow2_any<T, NT, 4>(buf, n, G, p, lp, roots, fin, fo, fz);
-    else stage_pow2_any<T, NT, 8>(buf, n, G, p, lp, roots, fin, fo, fz);
-    p <<= rr;
-    lp += rr;
-    ++st;
-  }
-  while (st < nst) {
-    const int fi = (st == 0) ? fin : kInPlain;
-    const int fo = (st == nst - 1) ? fout : kOutPlain;
-    stage_pow2_any<T, NT, 16>(buf, n, G, p, lp, roots, fi, fo, fz);
-    p <<= 4;
-    lp += 4;
-    ++st;
-  }
 }
 
 // Mixed-radix Stockham FFT of G channels of length n = 4i: radix-4 stages over
 // the power-of-two part, one radix-2 stage if needed, then one direct stage
 // per remaining odd prime factor (all <= kMaxDirectPrime on this path).
 template <typename T, int NT>
-__device__ void fft_mixed(cplx<T> *buf, int n, int G, const cplx<T> *__restrict__ roots) {
-  const Roots<cplx<T>> rg{roots, -1};
-  int rem = n, p = 1, lp = 0;
-  const Fuse<T> fz{nullptr, nullptr, 0, (T)0};
+__device__ __noinline__ void fft_mixed(cplx<T> *buf, int n, int G, int pad, const cplx<T> *__restrict__ roots) {
+  int rem = n, p = 1;
   while ((rem & 3) == 0) {
-    stage_pow2<T, NT, 4, kInPlain, kOutPlain>(buf, n, G, p, lp, rg, fz);
+    stage_mix_p2<T, NT, 4>(buf, n, G, p, pad, roots);
     p <<= 2;
-    lp += 2;
     rem >>= 2;
   }
   if ((rem & 1) == 0) {
-    stage_pow2<T, NT, 2, kInPlain, kOutPlain>(buf, n, G, p, lp, rg, fz);
+    stage_mix_p2<T, NT, 2>(buf, n, G, p, pad, roots);
     p <<= 1;
-    lp += 1;
     rem >>= 1;
   }
   while (rem > 1) {
@@ -343,25 +403,10 @@ __device__ void fft_mixed(cplx<T> *buf, int n, int G, const cplx<T> *__restrict_
         R = r;
         break;
       }
-    stage_odd<T, NT>(buf, n, G, p, R, roots);
+    stage_odd<T, NT>(buf, n, G, p, R, pad, roots);
     p *= R;
     rem /= R;
   }
-}
-
-// Bluestein DFT of one channel of length n (Eq. (17)-(23)): with the chirp
-// c_j = exp(-i pi j^2/n), X_k = c_k sum_j (x_j c_j) conj(c_{k-j}); the
-// convolution is done cyclically on the power-of-two length M >= 2n-1 with
-// the precomputed transform bhat of conj(c) and two power-of-two FFTs in LDS
-// (the inverse one through conjugation).  The chirp products, the zero
-// padding and the product with bhat are fused into the first and last FFT
-// stages.  On return buf[0..n) holds X.
-template <typename T, int NT>
-__device__ void fft_bluestein(cplx<T> *buf, int n, int M, const cplx<T> *__restrict__ chirp,
-                              const cplx<T> *__restrict__ bhat, const cplx<T> *tq) {
-  const Fuse<T> fz{chirp, bhat, n, (T)1 / (T)M};
-  fft_pow2<T, NT>(buf, M, 1, tq, kInChirp, kOutBhat, fz);
-  fft_pow2<T, NT>(buf, M, 1, tq, kInPlain, kOutChirp, fz);
 }
 
 // Octant root table of the power-of-two length N into LDS; the source is the
@@ -371,31 +416,45 @@ __device__ __forceinline__ void load_octant(cplx<T> *tq, const cplx<T> *__restri
   for (int r = threadIdx.x; r <= N / 8; r += NT) tq[r] = src[r * rs];
 }
 
-// Forward DFT of gc channels of ring-pair p held in buf (channel-major);
-// tq is LDS space for an octant root table.  Every thread of the workgroup
-// calls this (it synchronises internally).
+// LDS layout flag of a ring pass: the transform length is the ring length n,
+// or the Bluestein length M when M > 0.
+__device__ __forceinline__ int pass_pad(int n, int M) { return (M ? M : n) >= kPadMin; }
+
+// Forward DFT of gc channels of ring-pair p held in buf (channel-major, LDS
+// layout lidx(., pad)); tq is LDS space for an octant root table.  Every
+// thread of the workgroup calls this (it synchronises internally).
+//
+// Rings with a prime factor above kMaxDirectPrime (M > 0, one channel at a
+// time) take Bluestein's DFT (Eq. (17)-(23)): with the chirp
+// c_j = exp(-i pi j^2/n), X_k = c_k sum_j (x_j c_j) conj(c_{k-j}); the
+// convolution is done cyclically on the power-of-two length M >= 2n-1 with
+// the precomputed transform bhat of conj(c) and two power-of-two FFTs (the
+// inverse one through conjugation), the chirp products, the zero padding and
+// the product with bhat fused into their first and last stages.  One call
+// site of the power-of-two FFT serves both cases.
 template <typename T, int NT>
 __device__ __forceinline__ void ring_dft(const Tables &tb, int p, int M, cplx<T> *buf, cplx<T> *tq, int n, int gc,
-                                         bool tq_ready) {
-  if (M == 0) {
-    const cplx<T> *roots = TabOf<T>::roots(tb) + roots_offset(n >> 2);
-    if ((n & (n - 1)) == 0) {
-      if (!tq_ready) {
-        load_octant<T, NT>(tq, roots, n, 1);
-        __syncthreads();
-      }
-      fft_pow2<T, NT>(buf, n, gc, tq, kInPlain, kOutPlain, Fuse<T>{nullptr, nullptr, 0, (T)0});
-    } else {
-      fft_mixed<T, NT>(buf, n, gc, roots);
-    }
-  } else {
-    // Bluestein rings run one channel at a time (gc == 1)
-    if (!tq_ready) {
-      load_octant<T, NT>(tq, TabOf<T>::rootsP(tb), M, tb.mmax_bs / M);
-      __syncthreads();
-    }
-    const size_t co = roots_offset(n >> 2);
-    fft_bluestein<T, NT>(buf, n, M, TabOf<T>::chirp(tb) + co, TabOf<T>::bhat(tb) + tb.rp_bsoff[p], tq);
+                                         int pad, bool tq_ready) {
+  const bool p2 = (n & (n - 1)) == 0;
+  if (M == 0 && !p2) {
+    fft_mixed<T, NT>(buf, n, gc, pad, TabOf<T>::roots(tb) + roots_offset(n >> 2));
+    return;
+  }
+  const int N = M ? M : n;
+  if (!tq_ready) {
+    if (M) load_octant<T, NT>(tq, TabOf<T>::rootsP(tb), M, tb.mmax_bs / M);
+    else load_octant<T, NT>(tq, TabOf<T>::roots(tb) + roots_offset(n >> 2), n, 1);
+    __syncthreads();
+  }
+  const size_t co = roots_offset(n >> 2);
+  const Fuse<T> fz{TabOf<T>::chirp(tb) + co, M ? TabOf<T>::bhat(tb) + tb.rp_bsoff[p] : nullptr, n,
+                   (T)1 / (T)N};
+  const int logN = __builtin_ctz(N);
+  const int npass = M ? 2 : 1;
+  for (int ps = 0; ps < npass; ++ps) {
+    const int fin = (M && ps == 0) ? kInChirp : kInPlain;
+    const int fout = M ? (ps == 0 ? kOutBhat : kOutChirp) : kOutPlain;
+    fft_p2<T, NT>(buf, logN, gc, pad, tq, fz, fin, fout);
   }
 }
 
@@ -437,6 +496,8 @@ __global__ void __launch_bounds__(NT, (sizeof(T) == 4 && NT == 512) ? 4 : 1)
   const size_t npix = (size_t)tb.npix;
   const int Mbs = use_bs ? tb.rp_M[p] : 0;
   const int Gp = Mbs ? 1 : G;
+  const int pad = pass_pad(n, Mbs);
+#pragma unroll 1
   for (int b0 = bg0; b0 < bg1; b0 += Gp) {
     const int gc = min(Gp, bg1 - b0);
     for (int j = threadIdx.x; j < gc * n; j += NT) {
@@ -444,10 +505,10 @@ __global__ void __launch_bounds__(NT, (sizeof(T) == 4 && NT == 512) ? 4 : 1)
       const TIn *row = map + (size_t)(b0 + c) * npix;
       const T fN = load_as<T, TIn>(row + sN + jj);
       const T fS = equator ? (T)0 : load_as<T, TIn>(row + sS + jj);
-      buf[lp_idx(j)] = cmk<C>(fN + fS, fN - fS);
+      buf[lidx(j, pad)] = cmk<C>(fN + fS, fN - fS);
     }
     __syncthreads();
-    ring_dft<T, NT>(tb, p, Mbs, buf, tq, n, gc, b0 != bg0);
+    ring_dft<T, NT>(tb, p, Mbs, buf, tq, n, gc, pad, b0 != bg0);
     // E/O spectra for m = 0..L; one phase per m, channels contiguous
     for (int m = threadIdx.x; m < M; m += NT) {
       const int k = m % n;
@@ -458,8 +519,8 @@ __global__ void __launch_bounds__(NT, (sizeof(T) == 4 && NT == 512) ? 4 : 1)
       ph.y *= w;
       const size_t o = ((size_t)p * M + m) * B + b0;
       for (int c = 0; c < gc; ++c) {
-        const C Gk = buf[lp_idx(c * n + k)];
-        const C Gc = buf[lp_idx(c * n + kc)];
+        const C Gk = buf[lidx(c * n + k, pad)];
+        const C Gc = buf[lidx(c * n + kc, pad)];
         // U = DFT(fN+fS)[k] = (G[k] + conj(G[-k]))/2 ; V = DFT(fN-fS)[k] = (G[k] - conj(G[-k]))/(2i)
         const C U = cmk<C>((T)0.5 * (Gk.x + Gc.x), (T)0.5 * (Gk.y - Gc.y));
         const C V = cmk<C>((T)0.5 * (Gk.y + Gc.y), (T)0.5 * (Gc.x - Gk.x));
@@ -489,6 +550,8 @@ __global__ void __launch_bounds__(NT, (sizeof(T) == 4 && NT == 512) ? 4 : 1)
   const size_t npix = (size_t)tb.npix;
   const int Mbs = use_bs ? tb.rp_M[p] : 0;
   const int Gp = Mbs ? 1 : G;
+  const int pad = pass_pad(n, Mbs);
+#pragma unroll 1
   for (int b0 = bg0; b0 < bg1; b0 += Gp) {
     const int gc = min(Gp, bg1 - b0);
     for (int j = threadIdx.x; j < gc * n; j += NT) {
@@ -519,13 +582,13 @@ __global__ void __launch_bounds__(NT, (sizeof(T) == 4 && NT == 512) ? 4 : 1)
         cs = cadd(cs, cconj(b));
       }
       // h = C_N + i C_S ; store conj(h) so that a forward DFT gives conj(IDFT(h))
-      buf[lp_idx(c * n + k)] = cmk<C>(cn.x - cs.y, -(cn.y + cs.x));
+      buf[lidx(c * n + k, pad)] = cmk<C>(cn.x - cs.y, -(cn.y + cs.x));
     }
     __syncthreads();
-    ring_dft<T, NT>(tb, p, Mbs, buf, tq, n, gc, b0 != bg0);
+    ring_dft<T, NT>(tb, p, Mbs, buf, tq, n, gc, pad, b0 != bg0);
     for (int j = threadIdx.x; j < gc * n; j += NT) {
       const int c = j / n, jj = j - c * n;
-      const C F = buf[lp_idx(j)];  // IDFT(h) = conj(F): f_N = F.x, f_S = -F.y
+      const C F = buf[lidx(j, pad)];  // IDFT(h) = conj(F): f_N = F.x, f_S = -F.y
       TOut *row = map + (size_t)(b0 + c) * npix;
       store_as<TOut, T>(row + sN + jj, F.x);
       if (!equator) store_as<TOut, T>(row + sS + jj, -F.y);
