@@ -96,13 +96,20 @@ bool valid_geom(int nside, int lmax) {
   return true;
 }
 
+// map and alm are `in` / `out` or `out` / `in` depending on the direction
 int check_common(int nside, int lmax, int batch, int dtype, const void *in, const void *out, const void *tables,
-                 const void *work, size_t work_bytes, Tables *view) {
+                 const void *work, size_t work_bytes, Tables *view, bool map_in) {
   if (!valid_geom(nside, lmax) || batch < 1) return SHTX_ERR_ARG;
   if (dtype != SHTX_F64 && dtype != SHTX_F32 && dtype != SHTX_BF16) return SHTX_ERR_ARG;
   if (!in || !out || !tables || !work) return SHTX_ERR_ARG;
   if (nside > kMaxNside) return SHTX_ERR_UNSUPPORTED;
   if (reinterpret_cast<uintptr_t>(work) % 256 != 0) return SHTX_ERR_ARG;
+  {
+    const uintptr_t mp = reinterpret_cast<uintptr_t>(map_in ? in : out);
+    const uintptr_t ap = reinterpret_cast<uintptr_t>(map_in ? out : in);
+    if (mp % (dtype == SHTX_BF16 ? 8 : 16) != 0) return SHTX_ERR_ARG;
+    if (ap % (dtype == SHTX_F64 ? 16 : 8) != 0) return SHTX_ERR_ARG;
+  }
   {
     std::lock_guard<std::mutex> lk(g_mu);
     auto it = g_tables.find(tables);
@@ -308,7 +315,7 @@ size_t shtx_workspace_bytes(int nside, int lmax, int batch, int dtype) {
 int shtx_map2alm(int nside, int lmax, int batch, int dtype, const void *map, void *alm, const void *tables,
                  void *work, size_t work_bytes, void *stream) {
   Tables tb;
-  int s = check_common(nside, lmax, batch, dtype, map, alm, tables, work, work_bytes, &tb);
+  int s = check_common(nside, lmax, batch, dtype, map, alm, tables, work, work_bytes, &tb, true);
   if (s != SHTX_OK) return s;
   hipStream_t st = static_cast<hipStream_t>(stream);
   switch (dtype) {
@@ -327,7 +334,7 @@ int shtx_map2alm(int nside, int lmax, int batch, int dtype, const void *map, voi
 int shtx_alm2map(int nside, int lmax, int batch, int dtype, const void *alm, void *map, const void *tables,
                  void *work, size_t work_bytes, void *stream) {
   Tables tb;
-  int s = check_common(nside, lmax, batch, dtype, alm, map, tables, work, work_bytes, &tb);
+  int s = check_common(nside, lmax, batch, dtype, alm, map, tables, work, work_bytes, &tb, false);
   if (s != SHTX_OK) return s;
   if (dtype == SHTX_BF16) return SHTX_ERR_UNSUPPORTED;
   hipStream_t st = static_cast<hipStream_t>(stream);
@@ -341,7 +348,7 @@ int shtx_alm2map(int nside, int lmax, int batch, int dtype, const void *alm, voi
 int shtx_map2alm_backward(int nside, int lmax, int batch, int dtype, const void *grad_alm, void *grad_map,
                           const void *tables, void *work, size_t work_bytes, void *stream) {
   Tables tb;
-  int s = check_common(nside, lmax, batch, dtype, grad_alm, grad_map, tables, work, work_bytes, &tb);
+  int s = check_common(nside, lmax, batch, dtype, grad_alm, grad_map, tables, work, work_bytes, &tb, false);
   if (s != SHTX_OK) return s;
   hipStream_t st = static_cast<hipStream_t>(stream);
   const double w = 4.0 * M_PI / (double)tb.npix;
@@ -361,7 +368,7 @@ int shtx_map2alm_backward(int nside, int lmax, int batch, int dtype, const void 
 int shtx_alm2map_backward(int nside, int lmax, int batch, int dtype, const void *grad_map, void *grad_alm,
                           const void *tables, void *work, size_t work_bytes, void *stream) {
   Tables tb;
-  int s = check_common(nside, lmax, batch, dtype, grad_map, grad_alm, tables, work, work_bytes, &tb);
+  int s = check_common(nside, lmax, batch, dtype, grad_map, grad_alm, tables, work, work_bytes, &tb, true);
   if (s != SHTX_OK) return s;
   if (dtype == SHTX_BF16) return SHTX_ERR_UNSUPPORTED;
   hipStream_t st = static_cast<hipStream_t>(stream);

@@ -476,6 +476,43 @@ __device__ __forceinline__ bool fft_work(int Rp, int B, int G, int *p, int *b0, 
   return true;
 }
 
+// Four consecutive map pixels as T (the caller guarantees 4-element
+// alignment of p: ring starts and lengths are multiples of 4 pixels).
+template <typename T, typename S> __device__ __forceinline__ void load4(const S *p, T (&v)[4]);
+template <> __device__ __forceinline__ void load4<float, float>(const float *p, float (&v)[4]) {
+  const float4 q = *reinterpret_cast<const float4 *>(p);
+  v[0] = q.x;
+  v[1] = q.y;
+  v[2] = q.z;
+  v[3] = q.w;
+}
+template <> __device__ __forceinline__ void load4<double, double>(const double *p, double (&v)[4]) {
+  const double2 a = reinterpret_cast<const double2 *>(p)[0];
+  const double2 b = reinterpret_cast<const double2 *>(p)[1];
+  v[0] = a.x;
+  v[1] = a.y;
+  v[2] = b.x;
+  v[3] = b.y;
+}
+template <> __device__ __forceinline__ void load4<float, bf16_t>(const bf16_t *p, float (&v)[4]) {
+  const uint2 q = *reinterpret_cast<const uint2 *>(p);
+  v[0] = __uint_as_float(q.x << 16);
+  v[1] = __uint_as_float(q.x & 0xffff0000u);
+  v[2] = __uint_as_float(q.y << 16);
+  v[3] = __uint_as_float(q.y & 0xffff0000u);
+}
+
+// Two adjacent complex values (FP32: one 16-byte store).
+__device__ __forceinline__ void store_pair(float2 *p, float2 a, float2 b) {
+  *reinterpret_cast<float4 *>(p) = make_float4(a.x, a.y, b.x, b.y);
+}
+__device__ __forceinline__ void store_pair(double2 *p, double2 a, double2 b) {
+  p[0] = a;
+  p[1] = b;
+}
+
+constexpr int kLoadUnroll = 4;  // quads of pixels in flight per thread
+
 template <typename TIn, typename T, int NT>
 __global__ void __launch_bounds__(NT, (sizeof(T) == 4 && NT == 512) ? 4 : 1)
     k_ring_fft_fwd(Tables tb, int B, int G, int use_bs, int tq_off, const TIn *__restrict__ map,
@@ -495,42 +532,84 @@ __global__ void __launch_bounds__(NT, (sizeof(T) == 4 && NT == 512) ? 4 : 1)
   const int num = tb.rp_p0n[p], den = tb.rp_p0d[p];
   const size_t npix = (size_t)tb.npix;
   const int Mbs = use_bs ? tb.rp_M[p] : 0;
-  const int Gp = Mbs ? 1 : G;
   const int pad = pass_pad(n, Mbs);
+  const int Gp = Mbs ? 1 : G;
+  const int nq = n >> 2;  // quads of pixels per ring
+  const int tid = threadIdx.x;
 #pragma unroll 1
   for (int b0 = bg0; b0 < bg1; b0 += Gp) {
     const int gc = min(Gp, bg1 - b0);
-    for (int j = threadIdx.x; j < gc * n; j += NT) {
-      const int c = j / n, jj = j - c * n;
-      const TIn *row = map + (size_t)(b0 + c) * npix;
-      const T fN = load_as<T, TIn>(row + sN + jj);
-      const T fS = equator ? (T)0 : load_as<T, TIn>(row + sS + jj);
-      buf[lidx(j, pad)] = cmk<C>(fN + fS, fN - fS);
+    // rings -> LDS, packed as (f_N + f_S) + i (f_N - f_S); every load of the
+    // pass is issued before the LDS writes
+#pragma unroll 1
+    for (int q0 = tid; q0 < gc * nq; q0 += kLoadUnroll * NT) {
+      T fN[kLoadUnroll][4], fS[kLoadUnroll][4];
+#pragma unroll
+      for (int u = 0; u < kLoadUnroll; ++u) {
+        const int q = q0 + u * NT;
+        if (q < gc * nq) {
+          const int c = q / nq, j = 4 * (q - c * nq);
+          const TIn *row = map + (size_t)(b0 + c) * npix + j;
+          load4<T, TIn>(row + sN, fN[u]);
+          if (!equator) load4<T, TIn>(row + sS, fS[u]);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kLoadUnroll; ++u) {
+        const int q = q0 + u * NT;
+        if (q < gc * nq) {
+          const int c = q / nq, j = 4 * (q - c * nq);
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const T a = fN[u][e], b = equator ? (T)0 : fS[u][e];
+            buf[lidx(c * n + j + e, pad)] = cmk<C>(a + b, a - b);
+          }
+        }
+      }
     }
     __syncthreads();
     ring_dft<T, NT>(tb, p, Mbs, buf, tq, n, gc, pad, b0 != bg0);
     // E/O spectra for m = 0..L; one phase per m, channels contiguous
-    for (int m = threadIdx.x; m < M; m += NT) {
-      const int k = m % n;
+    const size_t obase = (size_t)p * M * B + b0;
+    const bool pairs = ((B | b0) & 1) == 0;  // channel pairs start 16-byte aligned
+    for (int m = tid; m < M; m += NT) {
+      const int k = m < n ? m : m % n;
       const int kc = (k == 0) ? 0 : n - k;
       const int red = (int)(((long long)m * num) % (2 * den));
       C ph = phase_pi<T>(red, den, (T)-1);
       ph.x *= w;
       ph.y *= w;
-      const size_t o = ((size_t)p * M + m) * B + b0;
-      for (int c = 0; c < gc; ++c) {
-        const C Gk = buf[lidx(c * n + k, pad)];
-        const C Gc = buf[lidx(c * n + kc, pad)];
-        // U = DFT(fN+fS)[k] = (G[k] + conj(G[-k]))/2 ; V = DFT(fN-fS)[k] = (G[k] - conj(G[-k]))/(2i)
-        const C U = cmk<C>((T)0.5 * (Gk.x + Gc.x), (T)0.5 * (Gk.y - Gc.y));
-        const C V = cmk<C>((T)0.5 * (Gk.y + Gc.y), (T)0.5 * (Gc.x - Gk.x));
-        XE[o + c] = cmul(ph, U);
-        XO[o + c] = cmul(ph, V);
+      C *xe = XE + obase + (size_t)m * B;
+      C *xo = XO + obase + (size_t)m * B;
+      int c = 0;
+      // U = DFT(fN+fS)[k] = (G[k] + conj(G[-k]))/2 ; V = DFT(fN-fS)[k] = (G[k] - conj(G[-k]))/(2i)
+      auto uv = [&](int cc, C &U, C &V) {
+        const C Gk = buf[lidx(cc * n + k, pad)];
+        const C Gc = buf[lidx(cc * n + kc, pad)];
+        U = cmul(ph, cmk<C>((T)0.5 * (Gk.x + Gc.x), (T)0.5 * (Gk.y - Gc.y)));
+        V = cmul(ph, cmk<C>((T)0.5 * (Gk.y + Gc.y), (T)0.5 * (Gc.x - Gk.x)));
+      };
+      if (pairs) {
+        for (; c + 1 < gc; c += 2) {
+          C U0, V0, U1, V1;
+          uv(c, U0, V0);
+          uv(c + 1, U1, V1);
+          store_pair(xe + c, U0, U1);
+          store_pair(xo + c, V0, V1);
+        }
+      }
+      for (; c < gc; ++c) {
+        C U, V;
+        uv(c, U, V);
+        xe[c] = U;
+        xo[c] = V;
       }
     }
     __syncthreads();
   }
 }
+
+constexpr int kFoldUnroll = 4;  // (k, channel) items per thread with loads in flight
 
 template <typename TOut, typename T, int NT>
 __global__ void __launch_bounds__(NT, (sizeof(T) == 4 && NT == 512) ? 4 : 1)
@@ -549,44 +628,79 @@ __global__ void __launch_bounds__(NT, (sizeof(T) == 4 && NT == 512) ? 4 : 1)
   const int num = tb.rp_p0n[p], den = tb.rp_p0d[p];
   const size_t npix = (size_t)tb.npix;
   const int Mbs = use_bs ? tb.rp_M[p] : 0;
-  const int Gp = Mbs ? 1 : G;
   const int pad = pass_pad(n, Mbs);
+  const int Gp = Mbs ? 1 : G;
+  const int tid = threadIdx.x;
+  // c_m = g_m exp(+i m phi0)
+  auto phased = [&](const C *src, int m) {
+    const int red = (int)(((long long)m * num) % (2 * den));
+    return cmul(src[(size_t)m * B], phase_pi<T>(red, den, (T)1));
+  };
 #pragma unroll 1
   for (int b0 = bg0; b0 < bg1; b0 += Gp) {
     const int gc = min(Gp, bg1 - b0);
-    for (int j = threadIdx.x; j < gc * n; j += NT) {
-      const int k = j / gc, c = j - k * gc;  // channel fastest: adjacent channels adjacent in memory
-      C cn = cmk<C>(0, 0), cs = cmk<C>(0, 0);
-      // positive frequencies m = k (mod n)
-      for (int m = k; m < M; m += n) {
-        const int red = (int)(((long long)m * num) % (2 * den));
-        const C ph = phase_pi<T>(red, den, (T)1);
-        const size_t o = ((size_t)p * M + m) * B + b0 + c;
-        C a = cmul(GN[o], ph);
-        C b = equator ? cmk<C>(0, 0) : cmul(GS[o], ph);
-        if (m == 0) {
-          a.y = 0;
-          b.y = 0;
+    const C *gn = GN + (size_t)p * M * B + b0;
+    const C *gs = GS + (size_t)p * M * B + b0;
+    // fold onto k = m mod n (positive frequencies) and k = -m mod n (negative,
+    // conj); the first term of each sum is loaded for kFoldUnroll items at
+    // once, further aliases (short rings) in a loop
+#pragma unroll 1
+    for (int j0 = tid; j0 < gc * n; j0 += kFoldUnroll * NT) {
+      C pn[kFoldUnroll], ps[kFoldUnroll], qn[kFoldUnroll], qs[kFoldUnroll];
+#pragma unroll
+      for (int u = 0; u < kFoldUnroll; ++u) {
+        const int j = j0 + u * NT;
+        const int k = j / gc, c = j - k * gc;  // channel fastest: adjacent channels adjacent in memory
+        const int m1 = k, m2 = (k == 0) ? n : n - k;
+        const bool ok = j < gc * n;
+        pn[u] = ps[u] = qn[u] = qs[u] = cmk<C>(0, 0);
+        if (ok && m1 < M) {
+          pn[u] = gn[(size_t)m1 * B + c];
+          if (!equator) ps[u] = gs[(size_t)m1 * B + c];
         }
-        cn = cadd(cn, a);
-        cs = cadd(cs, b);
+        if (ok && m2 < M) {
+          qn[u] = gn[(size_t)m2 * B + c];
+          if (!equator) qs[u] = gs[(size_t)m2 * B + c];
+        }
       }
-      // negative frequencies -m = k (mod n), m >= 1, contribute conj(c_m)
-      for (int m = (k == 0) ? n : n - k; m < M; m += n) {
-        const int red = (int)(((long long)m * num) % (2 * den));
-        const C ph = phase_pi<T>(red, den, (T)1);
-        const size_t o = ((size_t)p * M + m) * B + b0 + c;
-        const C a = cmul(GN[o], ph);
-        const C b = equator ? cmk<C>(0, 0) : cmul(GS[o], ph);
-        cn = cadd(cn, cconj(a));
-        cs = cadd(cs, cconj(b));
+#pragma unroll
+      for (int u = 0; u < kFoldUnroll; ++u) {
+        const int j = j0 + u * NT;
+        if (j >= gc * n) continue;
+        const int k = j / gc, c = j - k * gc;
+        C cn = cmk<C>(0, 0), cs = cmk<C>(0, 0);
+        const int m1 = k, m2 = (k == 0) ? n : n - k;
+        if (m1 < M) {
+          const int red = (int)(((long long)m1 * num) % (2 * den));
+          const C ph = phase_pi<T>(red, den, (T)1);
+          cn = cmul(pn[u], ph);
+          cs = cmul(ps[u], ph);
+          if (m1 == 0) {
+            cn.y = 0;
+            cs.y = 0;
+          }
+        }
+        if (m2 < M) {
+          const int red = (int)(((long long)m2 * num) % (2 * den));
+          const C ph = phase_pi<T>(red, den, (T)1);
+          cn = cadd(cn, cconj(cmul(qn[u], ph)));
+          cs = cadd(cs, cconj(cmul(qs[u], ph)));
+        }
+        for (int m = m1 + n; m < M; m += n) {
+          cn = cadd(cn, phased(gn + c, m));
+          if (!equator) cs = cadd(cs, phased(gs + c, m));
+        }
+        for (int m = m2 + n; m < M; m += n) {
+          cn = cadd(cn, cconj(phased(gn + c, m)));
+          if (!equator) cs = cadd(cs, cconj(phased(gs + c, m)));
+        }
+        // h = C_N + i C_S ; store conj(h) so that a forward DFT gives conj(IDFT(h))
+        buf[lidx(c * n + k, pad)] = cmk<C>(cn.x - cs.y, -(cn.y + cs.x));
       }
-      // h = C_N + i C_S ; store conj(h) so that a forward DFT gives conj(IDFT(h))
-      buf[lidx(c * n + k, pad)] = cmk<C>(cn.x - cs.y, -(cn.y + cs.x));
     }
     __syncthreads();
     ring_dft<T, NT>(tb, p, Mbs, buf, tq, n, gc, pad, b0 != bg0);
-    for (int j = threadIdx.x; j < gc * n; j += NT) {
+    for (int j = tid; j < gc * n; j += NT) {
       const int c = j / n, jj = j - c * n;
       const C F = buf[lidx(j, pad)];  // IDFT(h) = conj(F): f_N = F.x, f_S = -F.y
       TOut *row = map + (size_t)(b0 + c) * npix;

@@ -77,6 +77,17 @@ def test_validation_before_launch(fn):
     assert f(8, 15, 2, 1, FAKE, FAKE, FAKE, None, wb, None) == _lib.ERR_ARG
     # unaligned workspace
     assert f(8, 15, 2, 1, FAKE, FAKE, FAKE, FAKE + 8, wb, None) == _lib.ERR_ARG
+    # unaligned map (16 bytes; 8 for BF16) or alm (its complex element)
+    map_first = fn in ("shtx_map2alm", "shtx_alm2map_backward")
+
+    def args(map_off, alm_off):
+        return (FAKE + map_off, FAKE + alm_off) if map_first else (FAKE + alm_off, FAKE + map_off)
+    wb64 = L.shtx_workspace_bytes(8, 15, 2, 0)
+    assert f(8, 15, 2, 1, *args(8, 0), FAKE, FAKE, wb, None) == _lib.ERR_ARG
+    assert f(8, 15, 2, 1, *args(0, 4), FAKE, FAKE, wb, None) == _lib.ERR_ARG
+    assert f(8, 15, 2, 0, *args(0, 8), FAKE, FAKE, wb64, None) == _lib.ERR_ARG
+    # aligned variants pass validation up to the table lookup
+    assert f(8, 15, 2, 1, *args(0, 8), FAKE, FAKE, wb, None) == _lib.ERR_TABLES
     # unsupported nside
     assert f(4096, 15, 2, 1, FAKE, FAKE, FAKE, FAKE, wb, None) == _lib.ERR_UNSUPPORTED
     # tables never built for this pointer
