@@ -10,7 +10,8 @@ OK, ERR_ARG, ERR_UNSUPPORTED, ERR_WORKSPACE, ERR_HIP, ERR_TABLES = range(6)
 
 EXPORTS = ("shtx_version", "shtx_status_string", "shtx_tables_bytes", "shtx_tables_build",
            "shtx_tables_release", "shtx_tables_work", "shtx_workspace_bytes", "shtx_map2alm", "shtx_alm2map",
-           "shtx_map2alm_backward", "shtx_alm2map_backward", "shtx_profile_enable",
+           "shtx_map2alm_backward", "shtx_alm2map_backward", "shtx_iter_workspace_bytes",
+           "shtx_map2alm_iter", "shtx_profile_enable",
            "shtx_profile_reset", "shtx_profile_read", "shtx_stage_name")
 STAGES = ("ring_fft_fwd", "legendre_fwd", "alm_out", "alm_in", "legendre_inv", "ring_fft_inv")
 
@@ -52,6 +53,10 @@ def lib():
         f = getattr(L, name)
         f.argtypes = [i, i, i, i, vp, vp, vp, vp, sz, vp]
         f.restype = i
+    L.shtx_iter_workspace_bytes.argtypes = [i, i, i, i]
+    L.shtx_iter_workspace_bytes.restype = sz
+    L.shtx_map2alm_iter.argtypes = [i, i, i, i, vp, vp, i, vp, vp, sz, vp]
+    L.shtx_map2alm_iter.restype = i
     L.shtx_profile_enable.argtypes = [i]
     L.shtx_profile_enable.restype = i
     L.shtx_profile_reset.argtypes = []

@@ -17,16 +17,17 @@ template <typename TIn, typename T>
 hipError_t launch_ring_fft_fwd(Tables, int, const TIn *, const double *, double, cplx<T> *, cplx<T> *,
                                hipStream_t);
 template <typename TOut, typename T>
-hipError_t launch_ring_fft_inv(Tables, int, const cplx<T> *, const cplx<T> *, TOut *, hipStream_t);
+hipError_t launch_ring_fft_inv(Tables, int, const cplx<T> *, const cplx<T> *, const TOut *, TOut *, hipStream_t);
 template <typename T>
 hipError_t launch_legendre_fwd_valu(const Tables &, int, const cplx<T> *, const cplx<T> *, cplx<T> *, hipStream_t);
 template <typename T>
-hipError_t launch_legendre_inv_valu(const Tables &, int, const cplx<T> *, cplx<T> *, cplx<T> *, hipStream_t);
+hipError_t launch_legendre_inv_valu(const Tables &, int, const cplx<T> *, SynLayout, cplx<T> *, cplx<T> *,
+                                    hipStream_t);
 bool mfma_fwd_supported(const Tables &tb);
 hipError_t launch_legendre_fwd_mfma(const Tables &, int, const float2 *, const float2 *, float2 *, hipStream_t);
-hipError_t launch_legendre_inv_mfma(const Tables &, int, const float2 *, float2 *, float2 *, hipStream_t);
+hipError_t launch_legendre_inv_mfma(const Tables &, int, const float2 *, SynLayout, float2 *, float2 *, hipStream_t);
 template <typename T, typename TO>
-hipError_t launch_alm_out(int, int, const cplx<T> *, cplx<TO> *, double, double, hipStream_t);
+hipError_t launch_alm_out(int, int, const cplx<T> *, cplx<TO> *, double, double, int, hipStream_t);
 template <typename T, typename TI>
 hipError_t launch_alm_in(int, int, const cplx<TI> *, const double *, cplx<T> *, double, double, double,
                          hipStream_t);
@@ -124,9 +125,19 @@ template <typename T> struct Work {
   cplx<T> *specA, *specB, *almt;
 };
 
-template <typename T> Work<T> carve(void *work, int nside, int lmax, int batch) {
-  const size_t cs = sizeof(cplx<T>);
-  const size_t spec = (size_t)(lmax + 1) * (size_t)(2 * nside) * (size_t)batch * cs;
+// Channels of one spectrum buffer: the batch, rounded up to whole channel
+// slices of the synthesis layout.
+size_t spec_channels(int nside, int lmax, int mmax_bs, int batch, size_t cs) {
+  const SynLayout l = syn_layout(nside, lmax, mmax_bs, batch, cs);
+  return (size_t)l.ns * (size_t)l.G;
+}
+
+size_t spec_bytes(int nside, int lmax, int mmax_bs, int batch, size_t cs) {
+  return (size_t)(lmax + 1) * (size_t)(2 * nside) * spec_channels(nside, lmax, mmax_bs, batch, cs) * cs;
+}
+
+template <typename T> Work<T> carve(void *work, const Tables &tb, int batch) {
+  const size_t spec = spec_bytes(tb.nside, tb.lmax, tb.mmax_bs, batch, sizeof(cplx<T>));
   char *b = static_cast<char *>(work);
   Work<T> w;
   w.specA = reinterpret_cast<cplx<T> *>(b);
@@ -134,6 +145,8 @@ template <typename T> Work<T> carve(void *work, int nside, int lmax, int batch) 
   w.almt = reinterpret_cast<cplx<T> *>(b + 2 * align_up(spec, 256));
   return w;
 }
+
+constexpr int kMaxIter = 64;  // refinement iterations accepted by shtx_map2alm_iter
 
 int status_of(hipError_t e) { return e == hipSuccess ? SHTX_OK : SHTX_ERR_HIP; }
 
@@ -159,21 +172,21 @@ template <> hipError_t legendre_fwd<float>(const Tables &tb, int B, const float2
     return launch_legendre_fwd_mfma(tb, B, XE, XO, ALMT, st);
   return launch_legendre_fwd_valu<float>(tb, B, XE, XO, ALMT, st);
 }
-template <typename T> hipError_t legendre_inv(const Tables &tb, int B, const cplx<T> *ALMT, cplx<T> *GN,
-                                              cplx<T> *GS, hipStream_t st) {
-  return launch_legendre_inv_valu<T>(tb, B, ALMT, GN, GS, st);
+template <typename T> hipError_t legendre_inv(const Tables &tb, int B, const cplx<T> *ALMT, SynLayout lay,
+                                              cplx<T> *GN, cplx<T> *GS, hipStream_t st) {
+  return launch_legendre_inv_valu<T>(tb, B, ALMT, lay, GN, GS, st);
 }
-template <> hipError_t legendre_inv<float>(const Tables &tb, int B, const float2 *ALMT, float2 *GN, float2 *GS,
-                                           hipStream_t st) {
-  if (B >= kMfmaMinBatch && !force_valu()) return launch_legendre_inv_mfma(tb, B, ALMT, GN, GS, st);
-  return launch_legendre_inv_valu<float>(tb, B, ALMT, GN, GS, st);
+template <> hipError_t legendre_inv<float>(const Tables &tb, int B, const float2 *ALMT, SynLayout lay, float2 *GN,
+                                           float2 *GS, hipStream_t st) {
+  if (B >= kMfmaMinBatch && !force_valu()) return launch_legendre_inv_mfma(tb, B, ALMT, lay, GN, GS, st);
+  return launch_legendre_inv_valu<float>(tb, B, ALMT, lay, GN, GS, st);
 }
 
 // analysis chain: ring FFT -> Legendre -> caller layout with factors
 template <typename TIn, typename T>
 int run_analysis(const Tables &tb, int B, const TIn *map, cplx<T> *alm, const double *wtab, double wscale,
-                 double f0, double fm, void *work, hipStream_t st) {
-  Work<T> w = carve<T>(work, tb.nside, tb.lmax, B);
+                 double f0, double fm, void *work, hipStream_t st, int accumulate = 0) {
+  Work<T> w = carve<T>(work, tb, B);
   hipError_t e;
   {
     StageTimer t(kStFftFwd, st);
@@ -186,14 +199,14 @@ int run_analysis(const Tables &tb, int B, const TIn *map, cplx<T> *alm, const do
   }
   if (e != hipSuccess) return SHTX_ERR_HIP;
   StageTimer t(kStAlmOut, st);
-  return status_of(launch_alm_out<T, T>(tb.lmax, B, w.almt, alm, f0, fm, st));
+  return status_of(launch_alm_out<T, T>(tb.lmax, B, w.almt, alm, f0, fm, accumulate, st));
 }
 
 // synthesis chain: caller layout with factors -> Legendre -> ring FFT
 template <typename TOut, typename T>
 int run_synthesis(const Tables &tb, int B, const cplx<T> *alm, TOut *map, double s, double f0, double fm, void *work,
-                  hipStream_t st) {
-  Work<T> w = carve<T>(work, tb.nside, tb.lmax, B);
+                  hipStream_t st, const TOut *sub = nullptr) {
+  Work<T> w = carve<T>(work, tb, B);
   hipError_t e;
   {
     StageTimer t(kStAlmIn, st);
@@ -202,11 +215,12 @@ int run_synthesis(const Tables &tb, int B, const cplx<T> *alm, TOut *map, double
   if (e != hipSuccess) return SHTX_ERR_HIP;
   {
     StageTimer t(kStLegInv, st);
-    e = legendre_inv<T>(tb, B, w.almt, w.specA, w.specB, st);
+    e = legendre_inv<T>(tb, B, w.almt, syn_layout(tb.nside, tb.lmax, tb.mmax_bs, B, sizeof(cplx<T>)), w.specA,
+                        w.specB, st);
   }
   if (e != hipSuccess) return SHTX_ERR_HIP;
   StageTimer t(kStFftInv, st);
-  return status_of(launch_ring_fft_inv<TOut, T>(tb, B, w.specA, w.specB, map, st));
+  return status_of(launch_ring_fft_inv<TOut, T>(tb, B, w.specA, w.specB, sub, map, st));
 }
 
 }  // namespace
@@ -306,8 +320,12 @@ int shtx_tables_release(const void *tables) {
 size_t shtx_workspace_bytes(int nside, int lmax, int batch, int dtype) {
   if (!valid_geom(nside, lmax) || batch < 1) return 0;
   if (dtype != SHTX_F64 && dtype != SHTX_F32 && dtype != SHTX_BF16) return 0;
+  if (nside > kMaxNside) return 0;
   const size_t cs = dtype == SHTX_F64 ? 16 : 8;
-  const size_t spec = (size_t)(lmax + 1) * (size_t)(2 * nside) * (size_t)batch * cs;
+  size_t nbhat;
+  int mmax_bs;
+  bluestein_sizes(nside, &nbhat, &mmax_bs);
+  const size_t spec = spec_bytes(nside, lmax, mmax_bs, batch, cs);
   const size_t almt = nalm_of(lmax) * (size_t)batch * cs;
   return 2 * align_up(spec, 256) + align_up(almt, 256);
 }
@@ -377,6 +395,46 @@ int shtx_alm2map_backward(int nside, int lmax, int batch, int dtype, const void 
                                         static_cast<double2 *>(grad_alm), nullptr, 1.0, 1.0, 2.0, work, st);
   return run_analysis<float, float>(tb, batch, static_cast<const float *>(grad_map), static_cast<float2 *>(grad_alm),
                                     nullptr, 1.0, 1.0, 2.0, work, st);
+}
+
+size_t shtx_iter_workspace_bytes(int nside, int lmax, int batch, int dtype) {
+  if (dtype != SHTX_F64 && dtype != SHTX_F32) return 0;
+  const size_t base = shtx_workspace_bytes(nside, lmax, batch, dtype);
+  if (base == 0) return 0;
+  const size_t e = dtype == SHTX_F64 ? 8 : 4;
+  return base + align_up((size_t)batch * 12 * (size_t)nside * (size_t)nside * e, 256);
+}
+
+int shtx_map2alm_iter(int nside, int lmax, int batch, int dtype, const void *map, void *alm, int niter,
+                      const void *tables, void *work, size_t work_bytes, void *stream) {
+  if (niter < 0 || niter > kMaxIter) return SHTX_ERR_ARG;
+  if (dtype == SHTX_BF16) return SHTX_ERR_UNSUPPORTED;
+  Tables tb;
+  int s = check_common(nside, lmax, batch, dtype, map, alm, tables, work, work_bytes, &tb, true);
+  if (s != SHTX_OK) return s;
+  if (work_bytes < shtx_iter_workspace_bytes(nside, lmax, batch, dtype)) return SHTX_ERR_WORKSPACE;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  char *resid = static_cast<char *>(work) + shtx_workspace_bytes(nside, lmax, batch, dtype);
+  if (dtype == SHTX_F64) {
+    const double *f = static_cast<const double *>(map);
+    double2 *a = static_cast<double2 *>(alm);
+    double *r = reinterpret_cast<double *>(resid);
+    s = run_analysis<double, double>(tb, batch, f, a, tb.rp_w, 1.0, 1.0, 1.0, work, st);
+    for (int k = 0; k < niter && s == SHTX_OK; ++k) {
+      s = run_synthesis<double, double>(tb, batch, a, r, 1.0, 1.0, 1.0, work, st, f);
+      if (s == SHTX_OK) s = run_analysis<double, double>(tb, batch, r, a, tb.rp_w, 1.0, 1.0, 1.0, work, st, 1);
+    }
+    return s;
+  }
+  const float *f = static_cast<const float *>(map);
+  float2 *a = static_cast<float2 *>(alm);
+  float *r = reinterpret_cast<float *>(resid);
+  s = run_analysis<float, float>(tb, batch, f, a, tb.rp_w, 1.0, 1.0, 1.0, work, st);
+  for (int k = 0; k < niter && s == SHTX_OK; ++k) {
+    s = run_synthesis<float, float>(tb, batch, a, r, 1.0, 1.0, 1.0, work, st, f);
+    if (s == SHTX_OK) s = run_analysis<float, float>(tb, batch, r, a, tb.rp_w, 1.0, 1.0, 1.0, work, st, 1);
+  }
+  return s;
 }
 
 }  // extern "C"

@@ -86,6 +86,31 @@ inline void bluestein_sizes(int nside, size_t *total, int *mmax) {
   *mmax = mx;
 }
 
+// Ring FFT launch geometry (ring_fft.hip): workgroup size NT, channels per
+// workgroup G (the channel slice of a ring pair), LDS bytes, offset of the
+// twiddle table in LDS and whether Bluestein rings are transformed as such.
+struct FftGeom {
+  int NT, G, tq_off, use_bs;
+  size_t lds;
+};
+FftGeom fft_geometry(int nside, int mmax_bs, int batch, size_t csize);
+
+// Layout of the synthesis spectra g_m (Legendre output, ring FFT input):
+// per ring pair, slices of G channels (G of the ring FFT geometry), each slice
+// [m][G] contiguous -- element (p, c, m) at ((p ns + c/G) M + m) G + c%G, with
+// ns = ceil(batch/G).  A ring-FFT workgroup reads its slice as whole lines.
+struct SynLayout {
+  int G, ns, M;
+  __host__ __device__ size_t idx(int p, int c, int m) const {
+    return (((size_t)p * ns + c / G) * M + m) * G + c % G;
+  }
+  __host__ __device__ size_t size(int npairs) const { return (size_t)npairs * ns * M * G; }
+};
+inline SynLayout syn_layout(int nside, int lmax, int mmax_bs, int batch, size_t csize) {
+  const int G = fft_geometry(nside, mmax_bs, batch, csize).G;
+  return SynLayout{G, (batch + G - 1) / G, lmax + 1};
+}
+
 // Byte offsets of the pieces of the resident table buffer.
 struct TableOffsets {
   size_t rp_n, rp_sN, rp_sS, rp_p0n, rp_p0d;  // int32 [Rp]

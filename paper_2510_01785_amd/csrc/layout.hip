@@ -2,7 +2,8 @@
 // the transposed internal layout ALMT[idx(l,m)][b] of the Legendre kernels,
 // with the per-coefficient scale factors of each entry point.
 //
-//   to caller:   alm = f_m * ALMT           (Im of m = 0 set to 0)
+//   to caller:   alm = f_m * ALMT           (Im of m = 0 set to 0),
+//                or alm += f_m * ALMT       (accumulating, iterative refinement)
 //   from caller: ALMT = s * f_m * c_lm * alm (Im of m = 0 ignored)
 //
 // f_m is f0 for m = 0 and fm for m > 0; c_lm is the normalisation of the
@@ -16,7 +17,7 @@ constexpr int kTileL = 64;
 
 template <typename T, typename TO>
 __global__ void __launch_bounds__(256)
-    k_alm_out(int L, int B, const cplx<T> *__restrict__ ALMT, cplx<TO> *__restrict__ alm, T f0, T fm) {
+    k_alm_out(int L, int B, const cplx<T> *__restrict__ ALMT, cplx<TO> *__restrict__ alm, T f0, T fm, int acc) {
   using C = cplx<T>;
   using CO = cplx<TO>;
   __shared__ C tile[kTileL][17];
@@ -40,7 +41,13 @@ __global__ void __launch_bounds__(256)
       CO o;
       o.x = (TO)(f * v.x);
       o.y = (m == 0) ? (TO)0 : (TO)(f * v.y);
-      alm[(size_t)(b0 + b) * nalm + base + l] = o;
+      CO *dst = alm + (size_t)(b0 + b) * nalm + base + l;
+      if (acc) {
+        const CO prev = *dst;
+        o.x += prev.x;
+        o.y += prev.y;
+      }
+      *dst = o;
     }
     __syncthreads();
   }
@@ -80,9 +87,10 @@ __global__ void __launch_bounds__(256)
 }
 
 template <typename T, typename TO>
-hipError_t launch_alm_out(int L, int B, const cplx<T> *ALMT, cplx<TO> *alm, double f0, double fm, hipStream_t st) {
+hipError_t launch_alm_out(int L, int B, const cplx<T> *ALMT, cplx<TO> *alm, double f0, double fm, int acc,
+                          hipStream_t st) {
   const dim3 grid((L + 1 + kTileL - 1) / kTileL, L + 1);
-  hipLaunchKernelGGL((k_alm_out<T, TO>), grid, dim3(256), 0, st, L, B, ALMT, alm, (T)f0, (T)fm);
+  hipLaunchKernelGGL((k_alm_out<T, TO>), grid, dim3(256), 0, st, L, B, ALMT, alm, (T)f0, (T)fm, acc);
   return hipGetLastError();
 }
 
@@ -94,8 +102,10 @@ hipError_t launch_alm_in(int L, int B, const cplx<TI> *alm, const double *coefC,
   return hipGetLastError();
 }
 
-template hipError_t launch_alm_out<double, double>(int, int, const double2 *, double2 *, double, double, hipStream_t);
-template hipError_t launch_alm_out<float, float>(int, int, const float2 *, float2 *, double, double, hipStream_t);
+template hipError_t launch_alm_out<double, double>(int, int, const double2 *, double2 *, double, double, int,
+                                                   hipStream_t);
+template hipError_t launch_alm_out<float, float>(int, int, const float2 *, float2 *, double, double, int,
+                                                 hipStream_t);
 template hipError_t launch_alm_in<double, double>(int, int, const double2 *, const double *, double2 *, double,
                                                   double, double, hipStream_t);
 template hipError_t launch_alm_in<float, float>(int, int, const float2 *, const double *, float2 *, double, double,

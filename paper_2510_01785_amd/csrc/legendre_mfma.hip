@@ -44,9 +44,13 @@ __global__ void __launch_bounds__(256)
   const int2 it = tb.ck_items[item];
   const int m = it.x, l0 = it.y;
   const int L = tb.lmax, M = L + 1, Rp = tb.npairs;
-  const int tid = threadIdx.x, w = tid >> 6, j = tid & 63;
+  const int tid = threadIdx.x, w = __builtin_amdgcn_readfirstlane(tid >> 6), j = tid & 63;
   const int h = j >> 5, col = j & 31;
-  const bool colok = (b0 + (col >> 1)) < B;
+  // columns beyond the batch read channel B-1 (finite data; their outputs are not stored)
+  const int colc = (b0 + (col >> 1)) < B ? col : 2 * (B - 1 - b0) + (col & 1);
+  // floats per ring pair in X; the fast load path needs 32 of them in 32 bits
+  const size_t rowf = (size_t)M * B * 2;
+  const bool fast_rows = rowf * 32 * sizeof(float) < (size_t)0x7fffffff;
   {
     const double *Ag = coefA + alm_idx(m, m, L) - m;
     if (tid < kBlockL) sA[tid] = Ag[min(l0 + tid, L)];
@@ -71,13 +75,25 @@ __global__ void __launch_bounds__(256)
     const double z = qok ? tb.rp_z[q] : 0.0;
     // B operands: K-step s pairs ring c0+64w+s (lanes < 32) with ring +32 (lanes >= 32)
     float xe[32], xo[32];
+    const int rw = c0 + w * 64;  // first ring of this wave's slice (uniform)
+    if (fast_rows && rw + 64 <= Rp) {
+      // uniform row address per step, one 32-bit lane offset (half, column)
+      const unsigned voff = (unsigned)(h * 32 * rowf + colc);
+      const size_t o0 = ((size_t)rw * M + m) * B * 2 + (size_t)b0 * 2;
 #pragma unroll
-    for (int s = 0; s < 32; ++s) {
-      const int r = c0 + w * 64 + h * 32 + s;
-      const bool ok = colok && r < Rp;
-      const size_t o = (((size_t)r * M + m) * B + b0) * 2 + col;
-      xe[s] = ok ? xe_f[o] : 0.f;
-      xo[s] = ok ? xo_f[o] : 0.f;
+      for (int s = 0; s < 32; ++s) {
+        xe[s] = xe_f[o0 + s * rowf + voff];
+        xo[s] = xo_f[o0 + s * rowf + voff];
+      }
+    } else {
+      // rings beyond the last pair read the last pair (their lambda is zero)
+#pragma unroll
+      for (int s = 0; s < 32; ++s) {
+        const int r = min(rw + h * 32 + s, Rp - 1);
+        const size_t o = (((size_t)r * M + m) * B + b0) * 2 + colc;
+        xe[s] = xe_f[o];
+        xo[s] = xo_f[o];
+      }
     }
     double prv = 0.0, cur = 0.0;
 #pragma unroll
@@ -88,7 +104,6 @@ __global__ void __launch_bounds__(256)
 #pragma unroll 1
       for (int t8 = 0; t8 < kSubL / 8; ++t8) {
         const int tb8 = hb * kSubL + t8 * 8;
-        const int lb8 = l0 + tb8;
         double Ac[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) Ac[u] = sA[tb8 + u];
@@ -103,7 +118,8 @@ __global__ void __launch_bounds__(256)
             prv = cur;
             cur = nx;
           }
-          tw[(t8 * 8 + u) * kTileRS + j] = (lb8 + u <= L) ? (float)cur : 0.f;
+          // rows l > lmax only feed output rows that are never stored
+          tw[(t8 * 8 + u) * kTileRS + j] = (float)cur;
         }
       }
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -158,50 +174,115 @@ __global__ void __launch_bounds__(256)
   }
 }
 
-// Synthesis.  Workgroup = (m, chunk of 128 ring pairs), 4 waves of 32 rings;
-// lanes j and j+32 both run ring j's recurrence (the two K slots of a row) and
-// feed lambda_l / lambda_{l+2} (even MFMA) and lambda_{l+1} / lambda_{l+3} (odd
-// MFMA) against a_{l..l+3} of 16 channels.  Workgroups are dealt so that all
-// chunks of one m run on one XCD (consecutive workgroups go to consecutive
-// XCDs), sharing the a_m slab in L2.
-constexpr int kInvRings = 128;
+// Synthesis.  Workgroup = (m, chunk of 256 ring pairs), 4 waves of 64
+// rings, one ring per lane.  Per 8 steps of l every lane advances its ring's
+// recurrence by 8 values; v_permlane32_swap pairs them into the A operands
+// of the 32-ring halves (lanes 0-31: lambda_l, lanes 32-63: lambda_{l+2} of
+// the same 32 rings), so that with B = a_{l}, a_{l+2} (even MFMA) and
+// a_{l+1}, a_{l+3} (odd MFMA) of 16 channels each half takes 4 MFMAs per 8
+// steps and no ring's recurrence is computed twice.  Workgroups are dealt so
+// that all chunks of eight consecutive m run on one XCD (consecutive
+// workgroups go to consecutive XCDs): they share the a_m slabs in L2 and
+// together fill whole lines of the slice-major synthesis spectra.
+constexpr int kInvRings = 256;
 constexpr int kInvBlk = 64;  // l's staged per block
+
+// (lanes 0-31 of x | lanes 0-31 of y) and (lanes 32-63 of x | lanes 32-63 of y)
+__device__ __forceinline__ void pair_halves(float x, float y, float &lo, float &hi) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(y), false, false);
+  lo = __uint_as_float(r[0]);
+  hi = __uint_as_float(r[1]);
+}
+
+__device__ __forceinline__ void inv_block(const double *sAb, const float *sBb, int l0, int L, int ls, double2 sd,
+                                          double z, int wl, int wl0, int wl1, int h, int col, double &prv,
+                                          double &cur, f32x16 (&acc)[4]) {
+#pragma unroll 1
+  for (int u8 = 0; u8 < kInvBlk / 8; ++u8) {
+    const int lq = l0 + 8 * u8;
+    if (lq + 7 < wl) continue;  // no ring of the wave is active yet (state stays zero)
+    float lam[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const double nx = fma(sAb[8 * u8 + u] * z, cur, -prv);
+      if (u == 0) {
+        const bool inj = (lq == ls);
+        prv = inj ? sd.x : cur;
+        cur = inj ? sd.y : nx;
+      } else {
+        prv = cur;
+        cur = nx;
+      }
+      lam[u] = (float)cur;
+    }
+    if (lq + 7 > L) {  // last group: l beyond lmax contributes nothing
+#pragma unroll
+      for (int u = 0; u < 8; ++u) lam[u] = (lq + u <= L) ? lam[u] : 0.f;
+    }
+    float e0lo, e0hi, o0lo, o0hi, e1lo, e1hi, o1lo, o1hi;
+    pair_halves(lam[0], lam[2], e0lo, e0hi);
+    pair_halves(lam[1], lam[3], o0lo, o0hi);
+    pair_halves(lam[4], lam[6], e1lo, e1hi);
+    pair_halves(lam[5], lam[7], o1lo, o1hi);
+    const float *rb = sBb + (8 * u8 + 2 * h) * 32 + col;
+    const float b0 = rb[0], b1 = rb[32], b4 = rb[4 * 32], b5 = rb[5 * 32];
+    if (lq + 7 >= wl0) {
+      acc[0] = mfma32(e0lo, b0, acc[0]);
+      acc[1] = mfma32(o0lo, b1, acc[1]);
+      acc[0] = mfma32(e1lo, b4, acc[0]);
+      acc[1] = mfma32(o1lo, b5, acc[1]);
+    }
+    if (lq + 7 >= wl1) {
+      acc[2] = mfma32(e0hi, b0, acc[2]);
+      acc[3] = mfma32(o0hi, b1, acc[3]);
+      acc[2] = mfma32(e1hi, b4, acc[2]);
+      acc[3] = mfma32(o1hi, b5, acc[3]);
+    }
+  }
+}
 
 __global__ void __launch_bounds__(256)
     k_legendre_inv_mfma(Tables tb, int B, int b0, const double *__restrict__ coefA, const float2 *__restrict__ ALMT,
-                        float2 *__restrict__ GN, float2 *__restrict__ GS) {
+                        SynLayout lay, float2 *__restrict__ GN, float2 *__restrict__ GS) {
   const int L = tb.lmax, M = L + 1, Rp = tb.npairs;
   const int nch = (Rp + kInvRings - 1) / kInvRings;
   const int g = blockIdx.x;
   const int x = g & 7, q = g >> 3;
-  const int m = x + 8 * (q / nch);
-  const int chunk = q % nch;
+  // XCD x takes the octets x, x+8, ... of m; within an octet, m-major then chunk
+  const int oct = x + 8 * (q / (8 * nch));
+  const int r8 = q % (8 * nch);
+  const int m = 8 * oct + r8 / nch;
+  const int chunk = r8 % nch;
   if (m > L) return;  // uniform
   const int tid = threadIdx.x, w = tid >> 6, j = tid & 63;
   const int h = j >> 5, col = j & 31;
-  const int p = chunk * kInvRings + w * 32 + col;
+  const int p = chunk * kInvRings + w * 64 + j;
   const bool pok = p < Rp;
   const bool colok = (b0 + (col >> 1)) < B;
   const double z = pok ? tb.rp_z[p] : 0.0;
   const int ls = pok ? tb.seed_l[(size_t)m * Rp + p] : L + 1;
   const double2 sd = pok ? tb.seed_v[(size_t)m * Rp + p] : make_double2(0.0, 0.0);
-  // first l any ring of the workgroup needs
+  // first l any ring of the workgroup / wave / 32-ring half needs
   __shared__ int s_lb;
   __shared__ float sB[2][kInvBlk][32];
   __shared__ double sA[2][kInvBlk];
   if (tid == 0) s_lb = L + 1;
   __syncthreads();
   atomicMin(&s_lb, ls);
-  int wl = ls;
+  int wh = ls;
 #pragma unroll
-  for (int o = 1; o < 64; o <<= 1) wl = min(wl, __shfl_xor(wl, o));
+  for (int o = 1; o < 32; o <<= 1) wh = min(wh, __shfl_xor(wh, o));
+  const int wl0 = __builtin_amdgcn_readfirstlane(wh);
+  const int wl1 = __shfl(wh, 32);
+  const int wl1u = __builtin_amdgcn_readfirstlane(wl1);
+  const int wl = min(wl0, wl1u);
   __syncthreads();
   const int lb = s_lb;
   const double *Ag = coefA + alm_idx(m, m, L) - m;
   const float *ag = reinterpret_cast<const float *>(ALMT) + ((alm_idx(m, m, L) - m) * B + b0) * 2;
   const size_t arow = (size_t)B * 2;
   // staging of one block: rows l0..l0+kInvBlk-1 of a (32 floats each, 8 per
-  // thread) and their recurrence coefficients
+  // thread, zero beyond lmax) and their recurrence coefficients
   const int srow = tid >> 2, scol = (tid & 3) * 8;
   float stg[8];
   double stgA = 0.0;
@@ -220,9 +301,11 @@ __global__ void __launch_bounds__(256)
     for (int e = 0; e < 8; ++e) sB[buf][srow][scol + e] = stg[e];
     if (tid < kInvBlk) sA[buf][tid] = stgA;
   };
-  f32x16 acc_e, acc_o;
+  f32x16 acc[4];
 #pragma unroll
-  for (int r = 0; r < 16; ++r) acc_e[r] = acc_o[r] = 0.f;
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[a][r] = 0.f;
   double prv = 0.0, cur = 0.0;
   if (lb <= L) {
     fetch(lb);
@@ -234,29 +317,7 @@ __global__ void __launch_bounds__(256)
     const bool more = l0 + kInvBlk <= L;
     if (more) fetch(l0 + kInvBlk);
     if (wl <= l0 + kInvBlk - 1) {  // some ring of this wave is active in the block
-#pragma unroll 1
-      for (int u8 = 0; u8 < kInvBlk / 8; ++u8) {
-        const int lq = l0 + 8 * u8;
-        float lam[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          const double nx = fma(sA[buf][8 * u8 + u] * z, cur, -prv);
-          if (u == 0) {
-            const bool inj = (lq == ls);
-            prv = inj ? sd.x : cur;
-            cur = inj ? sd.y : nx;
-          } else {
-            prv = cur;
-            cur = nx;
-          }
-          lam[u] = (lq + u <= L) ? (float)cur : 0.f;
-        }
-        const float *rb = &sB[buf][8 * u8 + 2 * h][col];
-        acc_e = mfma32(h ? lam[2] : lam[0], rb[0], acc_e);
-        acc_o = mfma32(h ? lam[3] : lam[1], rb[32], acc_o);
-        acc_e = mfma32(h ? lam[6] : lam[4], rb[4 * 32], acc_e);
-        acc_o = mfma32(h ? lam[7] : lam[5], rb[5 * 32], acc_o);
-      }
+      inv_block(sA[buf], &sB[buf][0][0], l0, L, ls, sd, z, wl, wl0, wl1u, h, col, prv, cur, acc);
     }
     if (more) stash(buf ^ 1);
     __syncthreads();
@@ -265,14 +326,20 @@ __global__ void __launch_bounds__(256)
   if (!colok) return;
   float *gn = reinterpret_cast<float *>(GN);
   float *gs = reinterpret_cast<float *>(GS);
+  const int c = b0 + (col >> 1);
+  const size_t ringf = (size_t)lay.ns * lay.M * lay.G * 2;  // floats per ring pair
+  const size_t cofs = lay.idx(0, c, m) * 2 + (col & 1);
 #pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    const int i = 8 * (r >> 2) + 4 * h + (r & 3);
-    const int pr = chunk * kInvRings + w * 32 + i;
-    if (pr >= Rp) continue;
-    const size_t o = (((size_t)pr * M + m) * B + b0) * 2 + col;
-    gn[o] = acc_e[r] + acc_o[r];
-    gs[o] = acc_e[r] - acc_o[r];
+  for (int hh = 0; hh < 2; ++hh) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int i = 8 * (r >> 2) + 4 * h + (r & 3);
+      const int pr = chunk * kInvRings + w * 64 + hh * 32 + i;
+      if (pr >= Rp) continue;
+      const size_t o = (size_t)pr * ringf + cofs;
+      gn[o] = acc[2 * hh][r] + acc[2 * hh + 1][r];
+      gs[o] = acc[2 * hh][r] - acc[2 * hh + 1][r];
+    }
   }
 }
 
@@ -297,13 +364,14 @@ hipError_t launch_legendre_fwd_mfma(const Tables &tb, int B, const float2 *XE, c
   return hipGetLastError();
 }
 
-hipError_t launch_legendre_inv_mfma(const Tables &tb, int B, const float2 *ALMT, float2 *GN, float2 *GS,
-                                    hipStream_t st) {
+hipError_t launch_legendre_inv_mfma(const Tables &tb, int B, const float2 *ALMT, SynLayout lay, float2 *GN,
+                                    float2 *GS, hipStream_t st) {
   const int nch = (tb.npairs + kInvRings - 1) / kInvRings;
-  const int nm = (tb.lmax + 1 + 7) / 8;
+  const int noct = (tb.lmax + 1 + 7) / 8;
+  const int per_xcd = ((noct + 7) / 8) * 8 * nch;  // octets per XCD x 8 m x chunks
   for (int b0 = 0; b0 < B; b0 += 16)
-    hipLaunchKernelGGL(k_legendre_inv_mfma, dim3(8 * nm * nch), dim3(256), 0, st, tb, B, b0, tb.coefA, ALMT, GN,
-                       GS);
+    hipLaunchKernelGGL(k_legendre_inv_mfma, dim3(8 * per_xcd), dim3(256), 0, st, tb, B, b0, tb.coefA, ALMT, lay,
+                       GN, GS);
   return hipGetLastError();
 }
 

@@ -178,8 +178,8 @@ __global__ void __launch_bounds__(NT)
 // uniform loads; a ring joins at its seed l_s.
 template <typename T, int BG>
 __global__ void __launch_bounds__(256)
-    k_legendre_inv_valu(Tables tb, int B, int b0, const cplx<T> *__restrict__ ALMT, cplx<T> *__restrict__ GN,
-                        cplx<T> *__restrict__ GS) {
+    k_legendre_inv_valu(Tables tb, int B, int b0, const cplx<T> *__restrict__ ALMT, SynLayout lay,
+                        cplx<T> *__restrict__ GN, cplx<T> *__restrict__ GS) {
   using C = cplx<T>;
   const int m = blockIdx.y;
   const int p = blockIdx.x * 256 + threadIdx.x;
@@ -233,7 +233,7 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
   for (int b = 0; b < BG; ++b) {
     if (b0 + b >= B) continue;
-    const size_t o = ((size_t)p * M + m) * B + b0 + b;
+    const size_t o = lay.idx(p, b0 + b, m);
     GN[o] = cmk<C>(se[b][0] + so[b][0], se[b][1] + so[b][1]);
     GS[o] = cmk<C>(se[b][0] - so[b][0], se[b][1] - so[b][1]);
   }
@@ -263,12 +263,12 @@ hipError_t launch_legendre_fwd_valu(const Tables &tb, int B, const cplx<T> *XE, 
 }
 
 template <typename T>
-hipError_t launch_legendre_inv_valu(const Tables &tb, int B, const cplx<T> *ALMT, cplx<T> *GN, cplx<T> *GS,
-                                    hipStream_t st) {
+hipError_t launch_legendre_inv_valu(const Tables &tb, int B, const cplx<T> *ALMT, SynLayout lay, cplx<T> *GN,
+                                    cplx<T> *GS, hipStream_t st) {
   constexpr int BG = sizeof(T) == 8 ? 2 : 4;
   const dim3 grid((tb.npairs + 255) / 256, tb.lmax + 1);
   for (int b0 = 0; b0 < B; b0 += BG)
-    hipLaunchKernelGGL((k_legendre_inv_valu<T, BG>), grid, dim3(256), 0, st, tb, B, b0, ALMT, GN, GS);
+    hipLaunchKernelGGL((k_legendre_inv_valu<T, BG>), grid, dim3(256), 0, st, tb, B, b0, ALMT, lay, GN, GS);
   return hipGetLastError();
 }
 
@@ -276,9 +276,9 @@ template hipError_t launch_legendre_fwd_valu<double>(const Tables &, int, const 
                                                      hipStream_t);
 template hipError_t launch_legendre_fwd_valu<float>(const Tables &, int, const float2 *, const float2 *, float2 *,
                                                     hipStream_t);
-template hipError_t launch_legendre_inv_valu<double>(const Tables &, int, const double2 *, double2 *, double2 *,
-                                                     hipStream_t);
-template hipError_t launch_legendre_inv_valu<float>(const Tables &, int, const float2 *, float2 *, float2 *,
-                                                    hipStream_t);
+template hipError_t launch_legendre_inv_valu<double>(const Tables &, int, const double2 *, SynLayout, double2 *,
+                                                     double2 *, hipStream_t);
+template hipError_t launch_legendre_inv_valu<float>(const Tables &, int, const float2 *, SynLayout, float2 *,
+                                                    float2 *, hipStream_t);
 
 }  // namespace shtx

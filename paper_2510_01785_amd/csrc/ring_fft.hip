@@ -614,7 +614,7 @@ constexpr int kFoldUnroll = 4;  // (k, channel) items per thread with loads in f
 template <typename TOut, typename T, int NT>
 __global__ void __launch_bounds__(NT, (sizeof(T) == 4 && NT == 512) ? 4 : 1)
     k_ring_fft_inv(Tables tb, int B, int G, int use_bs, int tq_off, const cplx<T> *__restrict__ GN,
-                   const cplx<T> *__restrict__ GS, TOut *__restrict__ map) {
+                   const cplx<T> *__restrict__ GS, const TOut *__restrict__ sub, TOut *__restrict__ map) {
   using C = cplx<T>;
   extern __shared__ unsigned char smem_raw[];
   C *buf = reinterpret_cast<C *>(smem_raw);
@@ -634,13 +634,16 @@ __global__ void __launch_bounds__(NT, (sizeof(T) == 4 && NT == 512) ? 4 : 1)
   // c_m = g_m exp(+i m phi0)
   auto phased = [&](const C *src, int m) {
     const int red = (int)(((long long)m * num) % (2 * den));
-    return cmul(src[(size_t)m * B], phase_pi<T>(red, den, (T)1));
+    return cmul(src[(size_t)m * G], phase_pi<T>(red, den, (T)1));
   };
+  // this workgroup's channel slice [m][G] of the synthesis spectra
+  const int ns = (B + G - 1) / G;
+  const size_t sbase = ((size_t)p * ns + bg0 / G) * M * G;
 #pragma unroll 1
   for (int b0 = bg0; b0 < bg1; b0 += Gp) {
     const int gc = min(Gp, bg1 - b0);
-    const C *gn = GN + (size_t)p * M * B + b0;
-    const C *gs = GS + (size_t)p * M * B + b0;
+    const C *gn = GN + sbase + (b0 - bg0);
+    const C *gs = GS + sbase + (b0 - bg0);
     // fold onto k = m mod n (positive frequencies) and k = -m mod n (negative,
     // conj); the first term of each sum is loaded for kFoldUnroll items at
     // once, further aliases (short rings) in a loop
@@ -655,12 +658,12 @@ __global__ void __launch_bounds__(NT, (sizeof(T) == 4 && NT == 512) ? 4 : 1)
         const bool ok = j < gc * n;
         pn[u] = ps[u] = qn[u] = qs[u] = cmk<C>(0, 0);
         if (ok && m1 < M) {
-          pn[u] = gn[(size_t)m1 * B + c];
-          if (!equator) ps[u] = gs[(size_t)m1 * B + c];
+          pn[u] = gn[(size_t)m1 * G + c];
+          if (!equator) ps[u] = gs[(size_t)m1 * G + c];
         }
         if (ok && m2 < M) {
-          qn[u] = gn[(size_t)m2 * B + c];
-          if (!equator) qs[u] = gs[(size_t)m2 * B + c];
+          qn[u] = gn[(size_t)m2 * G + c];
+          if (!equator) qs[u] = gs[(size_t)m2 * G + c];
         }
       }
 #pragma unroll
@@ -700,50 +703,57 @@ __global__ void __launch_bounds__(NT, (sizeof(T) == 4 && NT == 512) ? 4 : 1)
     }
     __syncthreads();
     ring_dft<T, NT>(tb, p, Mbs, buf, tq, n, gc, pad, b0 != bg0);
-    for (int j = tid; j < gc * n; j += NT) {
-      const int c = j / n, jj = j - c * n;
-      const C F = buf[lidx(j, pad)];  // IDFT(h) = conj(F): f_N = F.x, f_S = -F.y
-      TOut *row = map + (size_t)(b0 + c) * npix;
-      store_as<TOut, T>(row + sN + jj, F.x);
-      if (!equator) store_as<TOut, T>(row + sS + jj, -F.y);
+    if (sub) {
+      // residual sub - S a of an iterative refinement (TOut = T)
+      for (int j = tid; j < gc * n; j += NT) {
+        const int c = j / n, jj = j - c * n;
+        const C F = buf[lidx(j, pad)];
+        const size_t r = (size_t)(b0 + c) * npix;
+        store_as<TOut, T>(map + r + sN + jj, load_as<T, TOut>(sub + r + sN + jj) - F.x);
+        if (!equator) store_as<TOut, T>(map + r + sS + jj, load_as<T, TOut>(sub + r + sS + jj) + F.y);
+      }
+    } else {
+      for (int j = tid; j < gc * n; j += NT) {
+        const int c = j / n, jj = j - c * n;
+        const C F = buf[lidx(j, pad)];  // IDFT(h) = conj(F): f_N = F.x, f_S = -F.y
+        TOut *row = map + (size_t)(b0 + c) * npix;
+        store_as<TOut, T>(row + sN + jj, F.x);
+        if (!equator) store_as<TOut, T>(row + sS + jj, -F.y);
+      }
     }
     __syncthreads();
   }
 }
 
-// Launch geometry: threads per workgroup, channels per mixed-radix group and
-// LDS bytes.  One stage holds NT * kFftOutMax complex values in registers, so
+// Launch geometry: threads per workgroup, channels per workgroup and LDS
+// bytes.  One stage holds NT * kFftOutMax complex values in registers, so
 // NT = 512 covers ring and Bluestein lengths up to 8192 without spilling; the
 // 16384-point Bluestein transforms of FP32 at nside 2048 take NT = 1024.
 // Bluestein rings need M complex values of LDS; where that does not fit
-// 128 KB (FP64 at nside 2048) every ring takes the mixed-radix path
-// (use_bs = 0).
+// (FP64 at nside 2048) every ring takes the mixed-radix path (use_bs = 0).
 constexpr size_t kMaxLds = 160 * 1024;  // LDS of one gfx950 workgroup
 
-template <typename T> int fft_threads(const Tables &tb) {
-  const int need = (4 * tb.nside > tb.mmax_bs) ? 4 * tb.nside : tb.mmax_bs;
-  return (sizeof(T) == 4 && need > 512 * kFftOutMax) ? 1024 : 512;
-}
-
-template <typename T> bool fft_geometry(const Tables &tb, int B, int NT, int *G, size_t *lds, int *tq_off) {
-  const int nmax = 4 * tb.nside;
-  const int cap = NT * kFftOutMax;  // complex values one stage can hold
-  int g = cap / nmax;
-  const int lds_cap = (int)((72 * 1024) / (nmax * sizeof(cplx<T>)));
-  if (g > lds_cap) g = lds_cap;
-  if (g > B) g = B;
-  if (g > 16) g = 16;
-  if (g < 1) g = 1;
-  *G = g;
-  size_t need = (size_t)g * nmax;
-  const bool use_bs = tb.mmax_bs > 0 && tb.mmax_bs <= cap &&
-                      (lds_elems(tb.mmax_bs) + tb.mmax_bs / 8 + 1) * sizeof(cplx<T>) <= kMaxLds;
-  if (use_bs && (size_t)tb.mmax_bs > need) need = tb.mmax_bs;
-  // quarter root table of the largest power-of-two length used
-  const int npow = use_bs && tb.mmax_bs > nmax ? tb.mmax_bs : nmax;
-  *tq_off = (int)lds_elems(need);
-  *lds = (lds_elems(need) + npow / 8 + 1) * sizeof(cplx<T>);
-  return use_bs;
+FftGeom fft_geometry(int nside, int mmax_bs, int batch, size_t csize) {
+  FftGeom g{};
+  const int nmax = 4 * nside;
+  const int need_pts = nmax > mmax_bs ? nmax : mmax_bs;
+  g.NT = (csize == 8 && need_pts > 512 * kFftOutMax) ? 1024 : 512;
+  const int cap = g.NT * kFftOutMax;  // complex values one stage can hold
+  int G = cap / nmax;
+  const int lds_cap = (int)((72 * 1024) / (nmax * csize));
+  if (G > lds_cap) G = lds_cap;
+  if (G > batch) G = batch;
+  if (G > 16) G = 16;
+  if (G < 1) G = 1;
+  g.G = G;
+  size_t need = (size_t)G * nmax;
+  g.use_bs = mmax_bs > 0 && mmax_bs <= cap && (lds_elems(mmax_bs) + mmax_bs / 8 + 1) * csize <= kMaxLds;
+  if (g.use_bs && (size_t)mmax_bs > need) need = mmax_bs;
+  // octant root table of the largest power-of-two length used
+  const int npow = g.use_bs && mmax_bs > nmax ? mmax_bs : nmax;
+  g.tq_off = (int)lds_elems(need);
+  g.lds = (lds_elems(need) + npow / 8 + 1) * csize;
+  return g;
 }
 
 inline unsigned fft_grid(int Rp, int B, int G) {
@@ -759,42 +769,38 @@ template <typename K> hipError_t allow_lds(K kern, size_t lds) {
 template <typename TIn, typename T>
 hipError_t launch_ring_fft_fwd(Tables tb, int B, const TIn *map, const double *wtab, double wscale, cplx<T> *XE,
                                cplx<T> *XO, hipStream_t st) {
-  const int NT = fft_threads<T>(tb);
-  int G, tq_off;
-  size_t lds;
-  const int use_bs = fft_geometry<T>(tb, B, NT, &G, &lds, &tq_off) ? 1 : 0;
-  const dim3 grid(fft_grid(tb.npairs, B, G));
-  if (NT == 512) {
+  const FftGeom g = fft_geometry(tb.nside, tb.mmax_bs, B, sizeof(cplx<T>));
+  const dim3 grid(fft_grid(tb.npairs, B, g.G));
+  if (g.NT == 512) {
     auto kern = k_ring_fft_fwd<TIn, T, 512>;
-    hipError_t e = allow_lds(kern, lds);
+    hipError_t e = allow_lds(kern, g.lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, grid, dim3(512), lds, st, tb, B, G, use_bs, tq_off, map, wtab, wscale, XE, XO);
+    hipLaunchKernelGGL(kern, grid, dim3(512), g.lds, st, tb, B, g.G, g.use_bs, g.tq_off, map, wtab, wscale, XE, XO);
   } else {
     auto kern = k_ring_fft_fwd<TIn, T, 1024>;
-    hipError_t e = allow_lds(kern, lds);
+    hipError_t e = allow_lds(kern, g.lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, grid, dim3(1024), lds, st, tb, B, G, use_bs, tq_off, map, wtab, wscale, XE, XO);
+    hipLaunchKernelGGL(kern, grid, dim3(1024), g.lds, st, tb, B, g.G, g.use_bs, g.tq_off, map, wtab, wscale, XE,
+                       XO);
   }
   return hipGetLastError();
 }
 
 template <typename TOut, typename T>
-hipError_t launch_ring_fft_inv(Tables tb, int B, const cplx<T> *GN, const cplx<T> *GS, TOut *map, hipStream_t st) {
-  const int NT = fft_threads<T>(tb);
-  int G, tq_off;
-  size_t lds;
-  const int use_bs = fft_geometry<T>(tb, B, NT, &G, &lds, &tq_off) ? 1 : 0;
-  const dim3 grid(fft_grid(tb.npairs, B, G));
-  if (NT == 512) {
+hipError_t launch_ring_fft_inv(Tables tb, int B, const cplx<T> *GN, const cplx<T> *GS, const TOut *sub, TOut *map,
+                               hipStream_t st) {
+  const FftGeom g = fft_geometry(tb.nside, tb.mmax_bs, B, sizeof(cplx<T>));
+  const dim3 grid(fft_grid(tb.npairs, B, g.G));
+  if (g.NT == 512) {
     auto kern = k_ring_fft_inv<TOut, T, 512>;
-    hipError_t e = allow_lds(kern, lds);
+    hipError_t e = allow_lds(kern, g.lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, grid, dim3(512), lds, st, tb, B, G, use_bs, tq_off, GN, GS, map);
+    hipLaunchKernelGGL(kern, grid, dim3(512), g.lds, st, tb, B, g.G, g.use_bs, g.tq_off, GN, GS, sub, map);
   } else {
     auto kern = k_ring_fft_inv<TOut, T, 1024>;
-    hipError_t e = allow_lds(kern, lds);
+    hipError_t e = allow_lds(kern, g.lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, grid, dim3(1024), lds, st, tb, B, G, use_bs, tq_off, GN, GS, map);
+    hipLaunchKernelGGL(kern, grid, dim3(1024), g.lds, st, tb, B, g.G, g.use_bs, g.tq_off, GN, GS, sub, map);
   }
   return hipGetLastError();
 }
@@ -805,11 +811,11 @@ template hipError_t launch_ring_fft_fwd<float, float>(Tables, int, const float *
                                                       float2 *, hipStream_t);
 template hipError_t launch_ring_fft_fwd<bf16_t, float>(Tables, int, const bf16_t *, const double *, double,
                                                        float2 *, float2 *, hipStream_t);
-template hipError_t launch_ring_fft_inv<double, double>(Tables, int, const double2 *, const double2 *, double *,
-                                                        hipStream_t);
-template hipError_t launch_ring_fft_inv<float, float>(Tables, int, const float2 *, const float2 *, float *,
-                                                      hipStream_t);
-template hipError_t launch_ring_fft_inv<bf16_t, float>(Tables, int, const float2 *, const float2 *, bf16_t *,
-                                                       hipStream_t);
+template hipError_t launch_ring_fft_inv<double, double>(Tables, int, const double2 *, const double2 *,
+                                                        const double *, double *, hipStream_t);
+template hipError_t launch_ring_fft_inv<float, float>(Tables, int, const float2 *, const float2 *, const float *,
+                                                      float *, hipStream_t);
+template hipError_t launch_ring_fft_inv<bf16_t, float>(Tables, int, const float2 *, const float2 *, const bf16_t *,
+                                                       bf16_t *, hipStream_t);
 
 }  // namespace shtx

@@ -125,6 +125,28 @@ def alm2map_raw(alm, nside, lmax):
     return _call("shtx_alm2map", nside, lmax, B, code, alm, out, alm.device)
 
 
+def map2alm_iter(maps, lmax, niter=3):
+    """Iteratively refined analysis (a <- a + A(f - S a), niter times) of
+    maps [B, Npix] float64/float32 -> alm [B, nalm] complex; no autograd."""
+    _check_device(maps)
+    squeeze = maps.dim() == 1
+    maps = (maps.unsqueeze(0) if squeeze else maps).contiguous()
+    code = _DTYPES[maps.dtype]
+    B, n = maps.shape
+    nside = nside_of(n)
+    out = torch.empty((B, nalm(lmax)), dtype=_ALM_DTYPE[code], device=maps.device)
+    L = _lib.lib()
+    tab = get_tables(nside, lmax, maps.device)
+    wb = L.shtx_iter_workspace_bytes(nside, lmax, B, code)
+    if wb == 0:
+        raise ValueError("map2alm_iter needs float64 or float32 maps")
+    work = torch.empty(wb, dtype=torch.uint8, device=maps.device)
+    st = L.shtx_map2alm_iter(nside, lmax, B, code, maps.data_ptr(), out.data_ptr(), int(niter), tab.data_ptr(),
+                             work.data_ptr(), wb, _stream_ptr(maps.device))
+    _lib.check("shtx_map2alm_iter", st)
+    return out[0] if squeeze else out
+
+
 def map2alm_backward_raw(grad_alm, nside, lmax, map_dtype):
     code = _DTYPES[map_dtype]
     grad_alm = grad_alm.contiguous().to(_ALM_DTYPE[code])
