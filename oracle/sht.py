@@ -15,7 +15,7 @@ north/south parity fold.
 import numpy as np
 
 from . import geometry
-from .legendre import legendre_analysis, legendre_synthesis
+from .legendre import lambda_table, legendre_analysis, legendre_synthesis
 
 
 def _ring_phase(g, r, mvals, sign):
@@ -30,19 +30,20 @@ def ring_weights_equal(nside):
     return np.full(R, 4.0 * np.pi / geometry.npix(nside))
 
 
-def ring_fourier_forward(maps, nside, lmax, ring_weights=None):
+def ring_fourier_forward(maps, nside, lmax, ring_weights=None, mvals=None):
     """F[r, m, b] = w_r * sum_j f[b, s_r + j] * exp(-i m phi_{r,j}).
 
     The sum over a ring is evaluated with numpy's FP64 FFT: for phi_{r,j} =
     phi0_r + 2 pi j / n_r it equals exp(-i m phi0_r) * DFT_n(f)[m mod n].
+    mvals selects the m (default 0..lmax); F is indexed by position in mvals.
     """
     g = geometry.ring_geometry(nside)
     maps = np.asarray(maps, dtype=np.float64)
     B = maps.shape[0]
     R = len(g["n"])
     w = ring_weights_equal(nside) if ring_weights is None else ring_weights
-    mvals = np.arange(lmax + 1)
-    F = np.empty((R, lmax + 1, B), dtype=np.complex128)
+    mvals = np.arange(lmax + 1) if mvals is None else np.asarray(mvals, dtype=np.int64)
+    F = np.empty((R, len(mvals), B), dtype=np.complex128)
     for r in range(R):
         s, n = int(g["start"][r]), int(g["n"][r])
         X = np.fft.fft(maps[:, s:s + n], axis=1)  # [B, n]
@@ -60,23 +61,29 @@ def ring_fourier_inverse(G, nside, lmax):
     """
     g = geometry.ring_geometry(nside)
     R, M, B = G.shape
-    mvals = np.arange(M)
     out = np.empty((B, geometry.npix(nside)))
     for r in range(R):
         s, n = int(g["start"][r]), int(g["n"][r])
-        c = G[r] * _ring_phase(g, r, mvals, +1.0)[:, None]  # [M, B]
-        rows = -(-M // n)
-        pos = np.zeros((rows * n, B), dtype=np.complex128)
-        pos[:M] = c
-        pos[0] = c[0].real
-        neg = np.zeros((rows * n, B), dtype=np.complex128)
-        neg[1:M] = np.conj(c[1:])
-        Cpos = pos.reshape(rows, n, B).sum(axis=0)       # k = m mod n
-        Cneg = neg.reshape(rows, n, B).sum(axis=0)       # indexed by m mod n
-        C = Cpos + Cneg[(-np.arange(n)) % n]              # k = -m mod n
-        f = np.fft.ifft(C, axis=0) * n
-        out[:, s:s + n] = f.real.T
+        out[:, s:s + n] = _ring_inverse(g, r, G[r])
     return out
+
+
+def _ring_inverse(g, r, Gr):
+    """Pixels [B, n_r] of ring r from its spectrum Gr [M, B] (m = 0..M-1)."""
+    M, B = Gr.shape
+    n = int(g["n"][r])
+    c = Gr * _ring_phase(g, r, np.arange(M), +1.0)[:, None]  # [M, B]
+    rows = -(-M // n)
+    pos = np.zeros((rows * n, B), dtype=np.complex128)
+    pos[:M] = c
+    pos[0] = c[0].real
+    neg = np.zeros((rows * n, B), dtype=np.complex128)
+    neg[1:M] = np.conj(c[1:])
+    Cpos = pos.reshape(rows, n, B).sum(axis=0)       # k = m mod n
+    Cneg = neg.reshape(rows, n, B).sum(axis=0)       # indexed by m mod n
+    C = Cpos + Cneg[(-np.arange(n)) % n]              # k = -m mod n
+    f = np.fft.ifft(C, axis=0) * n
+    return f.real.T
 
 
 def map2alm(maps, lmax, nside=None, ring_weights=None, nthreads=None):
@@ -96,6 +103,39 @@ def alm2map(alm, nside, lmax, nthreads=None):
     g = geometry.ring_geometry(nside)
     G = legendre_synthesis(lmax, g["z"], g["sth"], alm, nthreads)
     return ring_fourier_inverse(G, nside, lmax)
+
+
+def map2alm_m(maps, lmax, nside, ms):
+    """Selected columns of map2alm: {m: alm[b, l - m] for l = m..lmax} for
+    each m in ms, from the same ring sums and lambda recurrence as map2alm
+    (for full-resolution spot checks where every m would be too slow)."""
+    maps = np.atleast_2d(np.asarray(maps, dtype=np.float64))
+    g = geometry.ring_geometry(nside)
+    F = ring_fourier_forward(maps, nside, lmax, mvals=ms)  # [R, len(ms), B]
+    out = {}
+    for i, m in enumerate(ms):
+        lam = lambda_table(lmax, int(m), g["z"], g["sth"])  # [lmax-m+1, R]
+        out[int(m)] = (lam @ F[:, i, :]).T                   # [B, lmax-m+1]
+    return out
+
+
+def alm2map_rings(alm, nside, lmax, rings):
+    """Selected rings of alm2map: {r: maps[b, s_r : s_r + n_r]} for each ring
+    index r (0-based, north to south), from the same Legendre sums and ring
+    Fourier synthesis as alm2map."""
+    alm = np.atleast_2d(np.asarray(alm, dtype=np.complex128)).copy()
+    alm[:, :lmax + 1] = alm[:, :lmax + 1].real
+    g = geometry.ring_geometry(nside)
+    rings = [int(r) for r in rings]
+    B = alm.shape[0]
+    G = np.zeros((len(rings), lmax + 1, B), dtype=np.complex128)
+    z = np.asarray(g["z"])[rings]
+    sth = np.asarray(g["sth"])[rings]
+    for m in range(lmax + 1):
+        lam = lambda_table(lmax, m, z, sth)                  # [lmax-m+1, nr]
+        a = alm[:, geometry.alm_index(m, m, lmax):geometry.alm_index(lmax, m, lmax) + 1]
+        G[:, m, :] = lam.T @ a.T
+    return {r: _ring_inverse(g, r, G[i]) for i, r in enumerate(rings)}
 
 
 def _m_of_index(lmax):

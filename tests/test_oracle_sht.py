@@ -12,6 +12,7 @@ import pytest
 from scipy.special import sph_harm_y
 
 from oracle import brute, geometry, sht
+from paper_2510_01785_amd import synth
 
 
 CASES = [(1, 0), (1, 2), (1, 3), (2, 3), (2, 5), (2, 7), (4, 7), (4, 11),
@@ -104,3 +105,20 @@ def test_odd_parity_vanishes_on_equator():
         lam = legendre.lambda_table(40, m, np.array([0.0]), np.array([1.0]))[:, 0]
         ls = np.arange(m, 41)
         assert np.all(lam[(ls + m) % 2 == 1] == 0.0)
+
+
+def test_sampled_outputs_match_full_transforms():
+    """map2alm_m / alm2map_rings (the full-resolution spot-check forms) return
+    exactly the corresponding columns / rings of map2alm / alm2map."""
+    nside, lmax = 16, 40
+    f = synth.white_map(3, 2, geometry.npix(nside))
+    a = sht.map2alm(f, lmax, nside)
+    for m, v in sht.map2alm_m(f, lmax, nside, [0, 3, 17, 40]).items():
+        ref = a[:, geometry.alm_index(m, m, lmax):geometry.alm_index(lmax, m, lmax) + 1]
+        assert np.allclose(v, ref, rtol=0, atol=1e-14)
+    alm = synth.random_alm(4, 2, lmax)
+    mp = sht.alm2map(alm, nside, lmax)
+    g = geometry.ring_geometry(nside)
+    for r, v in sht.alm2map_rings(alm, nside, lmax, [0, 5, 31, 62]).items():
+        s0, n = int(g["start"][r]), int(g["n"][r])
+        assert np.allclose(v, mp[:, s0:s0 + n], rtol=0, atol=1e-12)
