@@ -12,6 +12,11 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libshtx.so")
 SOURCES = ["api.hip", "tables.hip", "ring_fft.hip", "legendre_valu.hip", "legendre_mfma.hip", "layout.hip"]
+# Per-source flags.  The matrix-core kernels keep their accumulators in
+# ordinary VGPRs (gfx950's unified register file): with AGPR accumulators the
+# compiler copies them between the two register kinds around every
+# contraction phase of the analysis kernel.
+EXTRA = {"legendre_mfma.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
 
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
 
@@ -35,7 +40,7 @@ def build(verbose=False, jobs=None):
     procs = []
     for src in SOURCES:
         obj = os.path.join(objdir, src.replace(".hip", ".o"))
-        cmd = [HIPCC] + FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [HIPCC] + FLAGS + EXTRA.get(src, []) + ["-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))

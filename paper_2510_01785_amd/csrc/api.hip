@@ -326,7 +326,8 @@ size_t shtx_workspace_bytes(int nside, int lmax, int batch, int dtype) {
   int mmax_bs;
   bluestein_sizes(nside, &nbhat, &mmax_bs);
   const size_t spec = spec_bytes(nside, lmax, mmax_bs, batch, cs);
-  const size_t almt = nalm_of(lmax) * (size_t)batch * cs;
+  // coefficients [idx][batch] plus kCoefPad rows read (and masked) past lmax
+  const size_t almt = (nalm_of(lmax) + kCoefPad) * (size_t)batch * cs;
   return 2 * align_up(spec, 256) + align_up(almt, 256);
 }
 

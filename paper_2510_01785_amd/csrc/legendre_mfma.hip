@@ -174,18 +174,20 @@ __global__ void __launch_bounds__(256)
   }
 }
 
-// Synthesis.  Workgroup = (m, chunk of 256 ring pairs), 4 waves of 64
-// rings, one ring per lane.  Per 8 steps of l every lane advances its ring's
-// recurrence by 8 values; v_permlane32_swap pairs them into the A operands
-// of the 32-ring halves (lanes 0-31: lambda_l, lanes 32-63: lambda_{l+2} of
-// the same 32 rings), so that with B = a_{l}, a_{l+2} (even MFMA) and
-// a_{l+1}, a_{l+3} (odd MFMA) of 16 channels each half takes 4 MFMAs per 8
-// steps and no ring's recurrence is computed twice.  Workgroups are dealt so
-// that all chunks of eight consecutive m run on one XCD (consecutive
-// workgroups go to consecutive XCDs): they share the a_m slabs in L2 and
-// together fill whole lines of the slice-major synthesis spectra.
-constexpr int kInvRings = 256;
-constexpr int kInvBlk = 64;  // l's staged per block
+// Synthesis.  Workgroup = one wave = (m, chunk of 64 ring pairs), one ring
+// per lane.  Per 8 steps of l every lane advances its ring's recurrence by 8
+// values; v_permlane32_swap pairs them into the A operands of the 32-ring
+// halves (lanes 0-31: lambda_l, lanes 32-63: lambda_{l+2} of the same 32
+// rings), so that with B = a_{l}, a_{l+2} (even MFMA) and a_{l+1}, a_{l+3}
+// (odd MFMA) of 16 channels each half takes 4 MFMAs per 8 steps and no ring's
+// recurrence is computed twice.  The recurrence coefficients are wave-uniform
+// scalar loads and the B operands come straight from the coefficient slab
+// (L1/L2), one group ahead: no LDS, no barriers, and every wave starts at its
+// own rings' first non-negligible l.  Workgroups are dealt so that all chunks
+// of eight consecutive m run on one XCD (consecutive workgroups go to
+// consecutive XCDs): they share the a_m slabs in L2 and together fill whole
+// lines of the slice-major synthesis spectra.
+constexpr int kInvRings = 64;
 
 // (lanes 0-31 of x | lanes 0-31 of y) and (lanes 32-63 of x | lanes 32-63 of y)
 __device__ __forceinline__ void pair_halves(float x, float y, float &lo, float &hi) {
@@ -194,54 +196,7 @@ __device__ __forceinline__ void pair_halves(float x, float y, float &lo, float &
   hi = __uint_as_float(r[1]);
 }
 
-__device__ __forceinline__ void inv_block(const double *sAb, const float *sBb, int l0, int L, int ls, double2 sd,
-                                          double z, int wl, int wl0, int wl1, int h, int col, double &prv,
-                                          double &cur, f32x16 (&acc)[4]) {
-#pragma unroll 1
-  for (int u8 = 0; u8 < kInvBlk / 8; ++u8) {
-    const int lq = l0 + 8 * u8;
-    if (lq + 7 < wl) continue;  // no ring of the wave is active yet (state stays zero)
-    float lam[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const double nx = fma(sAb[8 * u8 + u] * z, cur, -prv);
-      if (u == 0) {
-        const bool inj = (lq == ls);
-        prv = inj ? sd.x : cur;
-        cur = inj ? sd.y : nx;
-      } else {
-        prv = cur;
-        cur = nx;
-      }
-      lam[u] = (float)cur;
-    }
-    if (lq + 7 > L) {  // last group: l beyond lmax contributes nothing
-#pragma unroll
-      for (int u = 0; u < 8; ++u) lam[u] = (lq + u <= L) ? lam[u] : 0.f;
-    }
-    float e0lo, e0hi, o0lo, o0hi, e1lo, e1hi, o1lo, o1hi;
-    pair_halves(lam[0], lam[2], e0lo, e0hi);
-    pair_halves(lam[1], lam[3], o0lo, o0hi);
-    pair_halves(lam[4], lam[6], e1lo, e1hi);
-    pair_halves(lam[5], lam[7], o1lo, o1hi);
-    const float *rb = sBb + (8 * u8 + 2 * h) * 32 + col;
-    const float b0 = rb[0], b1 = rb[32], b4 = rb[4 * 32], b5 = rb[5 * 32];
-    if (lq + 7 >= wl0) {
-      acc[0] = mfma32(e0lo, b0, acc[0]);
-      acc[1] = mfma32(o0lo, b1, acc[1]);
-      acc[0] = mfma32(e1lo, b4, acc[0]);
-      acc[1] = mfma32(o1lo, b5, acc[1]);
-    }
-    if (lq + 7 >= wl1) {
-      acc[2] = mfma32(e0hi, b0, acc[2]);
-      acc[3] = mfma32(o0hi, b1, acc[3]);
-      acc[2] = mfma32(e1hi, b4, acc[2]);
-      acc[3] = mfma32(o1hi, b5, acc[3]);
-    }
-  }
-}
-
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(64)
     k_legendre_inv_mfma(Tables tb, int B, int b0, const double *__restrict__ coefA, const float2 *__restrict__ ALMT,
                         SynLayout lay, float2 *__restrict__ GN, float2 *__restrict__ GS) {
   const int L = tb.lmax, M = L + 1, Rp = tb.npairs;
@@ -254,74 +209,110 @@ __global__ void __launch_bounds__(256)
   const int m = 8 * oct + r8 / nch;
   const int chunk = r8 % nch;
   if (m > L) return;  // uniform
-  const int tid = threadIdx.x, w = tid >> 6, j = tid & 63;
+  const int j = threadIdx.x;
   const int h = j >> 5, col = j & 31;
-  const int p = chunk * kInvRings + w * 64 + j;
+  const int p = chunk * kInvRings + j;
   const bool pok = p < Rp;
   const bool colok = (b0 + (col >> 1)) < B;
   const double z = pok ? tb.rp_z[p] : 0.0;
   const int ls = pok ? tb.seed_l[(size_t)m * Rp + p] : L + 1;
   const double2 sd = pok ? tb.seed_v[(size_t)m * Rp + p] : make_double2(0.0, 0.0);
-  // first l any ring of the workgroup / wave / 32-ring half needs
-  __shared__ int s_lb;
-  __shared__ float sB[2][kInvBlk][32];
-  __shared__ double sA[2][kInvBlk];
-  if (tid == 0) s_lb = L + 1;
-  __syncthreads();
-  atomicMin(&s_lb, ls);
+  // first l any ring of each 32-ring half needs (aligned to m + 8j like every seed)
   int wh = ls;
 #pragma unroll
   for (int o = 1; o < 32; o <<= 1) wh = min(wh, __shfl_xor(wh, o));
   const int wl0 = __builtin_amdgcn_readfirstlane(wh);
-  const int wl1 = __shfl(wh, 32);
-  const int wl1u = __builtin_amdgcn_readfirstlane(wl1);
-  const int wl = min(wl0, wl1u);
-  __syncthreads();
-  const int lb = s_lb;
-  const double *Ag = coefA + alm_idx(m, m, L) - m;
-  const float *ag = reinterpret_cast<const float *>(ALMT) + ((alm_idx(m, m, L) - m) * B + b0) * 2;
-  const size_t arow = (size_t)B * 2;
-  // staging of one block: rows l0..l0+kInvBlk-1 of a (32 floats each, 8 per
-  // thread, zero beyond lmax) and their recurrence coefficients
-  const int srow = tid >> 2, scol = (tid & 3) * 8;
-  float stg[8];
-  double stgA = 0.0;
-  auto fetch = [&](int l0) {
-    const int l = l0 + srow;
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int cc = scol + e;
-      const bool ok = l <= L && (b0 + (cc >> 1)) < B;
-      stg[e] = ok ? ag[(size_t)l * arow + cc] : 0.f;
-    }
-    if (tid < kInvBlk) stgA = Ag[min(l0 + tid, L)];
-  };
-  auto stash = [&](int buf) {
-#pragma unroll
-    for (int e = 0; e < 8; ++e) sB[buf][srow][scol + e] = stg[e];
-    if (tid < kInvBlk) sA[buf][tid] = stgA;
-  };
+  const int wl1 = __builtin_amdgcn_readfirstlane(__shfl(wh, 32));
+  const int wl = min(wl0, wl1);
   f32x16 acc[4];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc[a][r] = 0.f;
+  // A[l] of this m through the constant address space: wave-uniform indices
+  // become scalar loads into SGPRs
+  // (32-bit index arithmetic keeps the address on the scalar unit; nalm < 2^31)
+  typedef __attribute__((address_space(4))) const double cdouble;
+  const int aoff = m * (2 * L + 1 - m) / 2;  // alm_idx(m, m, L) - m
+  const cdouble *Ag = (const cdouble *)coefA + aoff;
+  // this lane's column of the coefficient slab a[l][col] (channels beyond the
+  // batch read channel B-1: finite data, outputs not stored)
+  const int colc = colok ? col : 2 * (B - 1 - b0) + (col & 1);
+  // slab of column m (uniform) and this lane's fixed offsets in it: B operands
+  // of the group starting at lq are rows lq + 2h + {0, 1, 4, 5}.  Rows past
+  // lmax (at most 7, inside the padded coefficient workspace) are read and
+  // then zeroed with their lambda in the last group.
+  const float *ag = reinterpret_cast<const float *>(ALMT) + ((size_t)aoff * B + b0) * 2;
+  const int arow = 2 * B;
+  const unsigned vo0 = (unsigned)(2 * h * arow + colc), vo1 = vo0 + arow, vo4 = vo0 + 4 * arow,
+                 vo5 = vo0 + 5 * arow;
+  auto fetchB = [&](int lq, float (&bv)[4]) {
+    const float *rp = ag + (size_t)lq * arow;
+    bv[0] = rp[vo0];
+    bv[1] = rp[vo1];
+    bv[2] = rp[vo4];
+    bv[3] = rp[vo5];
+  };
   double prv = 0.0, cur = 0.0;
-  if (lb <= L) {
-    fetch(lb);
-    stash(0);
+  float bn[4];
+  double an[8];  // A_l of the next group (scalar registers)
+  if (wl <= L) {
+    fetchB(wl, bn);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) an[u] = Ag[wl + u];
   }
-  __syncthreads();
-  int buf = 0;
-  for (int l0 = lb; l0 <= L; l0 += kInvBlk) {
-    const bool more = l0 + kInvBlk <= L;
-    if (more) fetch(l0 + kInvBlk);
-    if (wl <= l0 + kInvBlk - 1) {  // some ring of this wave is active in the block
-      inv_block(sA[buf], &sB[buf][0][0], l0, L, ls, sd, z, wl, wl0, wl1u, h, col, prv, cur, acc);
+#pragma unroll 1
+  for (int lq = wl; lq <= L; lq += 8) {
+    const float bc[4] = {bn[0], bn[1], bn[2], bn[3]};
+    double ac[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) ac[u] = an[u];
+    if (lq + 8 <= L) {  // next group's operands in flight (rows < lmax + 8)
+      fetchB(lq + 8, bn);
+#pragma unroll
+      for (int u = 0; u < 8; ++u) an[u] = Ag[lq + 8 + u];
     }
-    if (more) stash(buf ^ 1);
-    __syncthreads();
-    buf ^= 1;
+    float lam[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const double nx = fma(ac[u] * z, cur, -prv);
+      if (u == 0) {
+        const bool inj = (lq == ls);
+        prv = inj ? sd.x : cur;
+        cur = inj ? sd.y : nx;
+      } else {
+        prv = cur;
+        cur = nx;
+      }
+      lam[u] = (float)cur;
+    }
+    float bb[4] = {bc[0], bc[1], bc[2], bc[3]};
+    if (lq + 7 > L) {  // last group: l beyond lmax contributes nothing
+#pragma unroll
+      for (int u = 0; u < 8; ++u) lam[u] = (lq + u <= L) ? lam[u] : 0.f;
+      const int r0 = lq + 2 * h;
+      bb[0] = r0 <= L ? bb[0] : 0.f;
+      bb[1] = r0 + 1 <= L ? bb[1] : 0.f;
+      bb[2] = r0 + 4 <= L ? bb[2] : 0.f;
+      bb[3] = r0 + 5 <= L ? bb[3] : 0.f;
+    }
+    float e0lo, e0hi, o0lo, o0hi, e1lo, e1hi, o1lo, o1hi;
+    pair_halves(lam[0], lam[2], e0lo, e0hi);
+    pair_halves(lam[1], lam[3], o0lo, o0hi);
+    pair_halves(lam[4], lam[6], e1lo, e1hi);
+    pair_halves(lam[5], lam[7], o1lo, o1hi);
+    if (lq + 7 >= wl0) {
+      acc[0] = mfma32(e0lo, bb[0], acc[0]);
+      acc[1] = mfma32(o0lo, bb[1], acc[1]);
+      acc[0] = mfma32(e1lo, bb[2], acc[0]);
+      acc[1] = mfma32(o1lo, bb[3], acc[1]);
+    }
+    if (lq + 7 >= wl1) {
+      acc[2] = mfma32(e0hi, bb[0], acc[2]);
+      acc[3] = mfma32(o0hi, bb[1], acc[3]);
+      acc[2] = mfma32(e1hi, bb[2], acc[2]);
+      acc[3] = mfma32(o1hi, bb[3], acc[3]);
+    }
   }
   if (!colok) return;
   float *gn = reinterpret_cast<float *>(GN);
@@ -334,7 +325,7 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int i = 8 * (r >> 2) + 4 * h + (r & 3);
-      const int pr = chunk * kInvRings + w * 64 + hh * 32 + i;
+      const int pr = chunk * kInvRings + hh * 32 + i;
       if (pr >= Rp) continue;
       const size_t o = (size_t)pr * ringf + cofs;
       gn[o] = acc[2 * hh][r] + acc[2 * hh + 1][r];
@@ -370,7 +361,7 @@ hipError_t launch_legendre_inv_mfma(const Tables &tb, int B, const float2 *ALMT,
   const int noct = (tb.lmax + 1 + 7) / 8;
   const int per_xcd = ((noct + 7) / 8) * 8 * nch;  // octets per XCD x 8 m x chunks
   for (int b0 = 0; b0 < B; b0 += 16)
-    hipLaunchKernelGGL(k_legendre_inv_mfma, dim3(8 * per_xcd), dim3(256), 0, st, tb, B, b0, tb.coefA, ALMT, lay,
+    hipLaunchKernelGGL(k_legendre_inv_mfma, dim3(8 * per_xcd), dim3(64), 0, st, tb, B, b0, tb.coefA, ALMT, lay,
                        GN, GS);
   return hipGetLastError();
 }
