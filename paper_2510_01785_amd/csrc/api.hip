@@ -24,7 +24,8 @@ template <typename T>
 hipError_t launch_legendre_inv_valu(const Tables &, int, const cplx<T> *, SynLayout, cplx<T> *, cplx<T> *,
                                     hipStream_t);
 bool mfma_fwd_supported(const Tables &tb);
-hipError_t launch_legendre_fwd_mfma(const Tables &, int, const float2 *, const float2 *, float2 *, hipStream_t);
+hipError_t launch_legendre_fwd_mfma(const Tables &, int, const float2 *, const float2 *, float2 *, double, double, int,
+                                    hipStream_t);
 hipError_t launch_legendre_inv_mfma(const Tables &, int, const float2 *, SynLayout, float2 *, float2 *, hipStream_t);
 template <typename T, typename TO>
 hipError_t launch_alm_out(int, int, const cplx<T> *, cplx<TO> *, double, double, int, hipStream_t);
@@ -162,14 +163,21 @@ bool force_valu() {
   return v;
 }
 
+// Legendre step of the analysis.  Returns true in *direct when the kernel
+// wrote the caller's layout itself (matrix-core path: factors f0 / fm and the
+// accumulate mode applied in its epilogue); otherwise the coefficients are in
+// ALMT for k_alm_out.
 template <typename T> hipError_t legendre_fwd(const Tables &tb, int B, const cplx<T> *XE, const cplx<T> *XO,
-                                              cplx<T> *ALMT, hipStream_t st) {
+                                              cplx<T> *ALMT, cplx<T> *, double, double, int, bool *direct,
+                                              hipStream_t st) {
+  *direct = false;
   return launch_legendre_fwd_valu<T>(tb, B, XE, XO, ALMT, st);
 }
 template <> hipError_t legendre_fwd<float>(const Tables &tb, int B, const float2 *XE, const float2 *XO,
-                                           float2 *ALMT, hipStream_t st) {
-  if (B >= kMfmaMinBatch && mfma_fwd_supported(tb) && !force_valu())
-    return launch_legendre_fwd_mfma(tb, B, XE, XO, ALMT, st);
+                                           float2 *ALMT, float2 *alm, double f0, double fm, int accum, bool *direct,
+                                           hipStream_t st) {
+  *direct = B >= kMfmaMinBatch && mfma_fwd_supported(tb) && !force_valu();
+  if (*direct) return launch_legendre_fwd_mfma(tb, B, XE, XO, alm, f0, fm, accum, st);
   return launch_legendre_fwd_valu<float>(tb, B, XE, XO, ALMT, st);
 }
 template <typename T> hipError_t legendre_inv(const Tables &tb, int B, const cplx<T> *ALMT, SynLayout lay,
@@ -193,11 +201,13 @@ int run_analysis(const Tables &tb, int B, const TIn *map, cplx<T> *alm, const do
     e = launch_ring_fft_fwd<TIn, T>(tb, B, map, wtab, wscale, w.specA, w.specB, st);
   }
   if (e != hipSuccess) return SHTX_ERR_HIP;
+  bool direct = false;
   {
     StageTimer t(kStLegFwd, st);
-    e = legendre_fwd<T>(tb, B, w.specA, w.specB, w.almt, st);
+    e = legendre_fwd<T>(tb, B, w.specA, w.specB, w.almt, alm, f0, fm, accumulate, &direct, st);
   }
   if (e != hipSuccess) return SHTX_ERR_HIP;
+  if (direct) return SHTX_OK;
   StageTimer t(kStAlmOut, st);
   return status_of(launch_alm_out<T, T>(tb.lmax, B, w.almt, alm, f0, fm, accumulate, st));
 }

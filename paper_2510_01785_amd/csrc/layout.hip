@@ -12,75 +12,80 @@
 
 namespace shtx {
 
-// One workgroup per (m, tile of l); LDS tile transposes [l][b] <-> [b][l].
-constexpr int kTileL = 64;
+// A workgroup takes kLayoutThreads consecutive coefficient indices idx(l, m)
+// (m = 0 exactly for idx <= lmax) and 16 channels at a time, through an LDS
+// tile: the caller side alm[b][idx] is read / written along idx and the
+// internal side ALMT[idx][b] as one contiguous run, both coalesced.
+constexpr int kLayoutThreads = 256;
 
 template <typename T, typename TO>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(kLayoutThreads)
     k_alm_out(int L, int B, const cplx<T> *__restrict__ ALMT, cplx<TO> *__restrict__ alm, T f0, T fm, int acc) {
   using C = cplx<T>;
   using CO = cplx<TO>;
-  __shared__ C tile[kTileL][17];
-  const int m = blockIdx.y;
-  const int l0 = m + blockIdx.x * kTileL;
-  if (l0 > L) return;
-  const int nl = min(kTileL, L + 1 - l0);
-  const size_t base = alm_idx(l0, m, L);
+  __shared__ C tile[kLayoutThreads][17];
   const size_t nalm = nalm_of(L);
-  const T f = (m == 0) ? f0 : fm;
+  const size_t i0 = (size_t)blockIdx.x * kLayoutThreads;
+  const int ni = (int)min((size_t)kLayoutThreads, nalm - i0);
+  const int t = threadIdx.x;
+  const size_t idx = i0 + t;
+  const bool m0 = idx <= (size_t)L;
+  const T f = m0 ? f0 : fm;
   for (int b0 = 0; b0 < B; b0 += 16) {
     const int nb = min(16, B - b0);
-    for (int t = threadIdx.x; t < nl * nb; t += 256) {
-      const int l = t / nb, b = t - l * nb;
-      tile[l][b] = ALMT[(base + l) * B + b0 + b];
+    // ALMT rows i0..i0+ni-1, channels b0..b0+nb-1: one contiguous run per row
+    for (int q = t; q < ni * nb; q += kLayoutThreads) {
+      const int r = q / nb, b = q - r * nb;
+      tile[r][b] = ALMT[(i0 + r) * B + b0 + b];
     }
     __syncthreads();
-    for (int t = threadIdx.x; t < nl * nb; t += 256) {
-      const int b = t / nl, l = t - b * nl;
-      const C v = tile[l][b];
-      CO o;
-      o.x = (TO)(f * v.x);
-      o.y = (m == 0) ? (TO)0 : (TO)(f * v.y);
-      CO *dst = alm + (size_t)(b0 + b) * nalm + base + l;
-      if (acc) {
-        const CO prev = *dst;
-        o.x += prev.x;
-        o.y += prev.y;
+    if (t < ni) {
+      for (int b = 0; b < nb; ++b) {
+        const C v = tile[t][b];
+        CO o;
+        o.x = (TO)(f * v.x);
+        o.y = m0 ? (TO)0 : (TO)(f * v.y);
+        CO *dst = alm + (size_t)(b0 + b) * nalm + idx;
+        if (acc) {
+          const CO prev = *dst;
+          o.x += prev.x;
+          o.y += prev.y;
+        }
+        *dst = o;
       }
-      *dst = o;
     }
     __syncthreads();
   }
 }
 
 template <typename T, typename TI>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(kLayoutThreads)
     k_alm_in(int L, int B, const cplx<TI> *__restrict__ alm, const double *__restrict__ coefC,
              cplx<T> *__restrict__ ALMT, double s, double f0, double fm) {
   using C = cplx<T>;
-  __shared__ C tile[kTileL][17];
-  const int m = blockIdx.y;
-  const int l0 = m + blockIdx.x * kTileL;
-  if (l0 > L) return;
-  const int nl = min(kTileL, L + 1 - l0);
-  const size_t base = alm_idx(l0, m, L);
+  __shared__ C tile[kLayoutThreads][17];
   const size_t nalm = nalm_of(L);
-  const double f = s * ((m == 0) ? f0 : fm);
+  const size_t i0 = (size_t)blockIdx.x * kLayoutThreads;
+  const int ni = (int)min((size_t)kLayoutThreads, nalm - i0);
+  const int t = threadIdx.x;
+  const size_t idx = i0 + t;
+  const bool m0 = idx <= (size_t)L;
+  const double g = t < ni ? s * (m0 ? f0 : fm) * coefC[idx] : 0.0;
   for (int b0 = 0; b0 < B; b0 += 16) {
     const int nb = min(16, B - b0);
-    for (int t = threadIdx.x; t < nl * nb; t += 256) {
-      const int b = t / nl, l = t - b * nl;
-      const cplx<TI> v = alm[(size_t)(b0 + b) * nalm + base + l];
-      const double g = f * coefC[base + l];
-      C o;
-      o.x = (T)(g * (double)v.x);
-      o.y = (m == 0) ? (T)0 : (T)(g * (double)v.y);
-      tile[l][b] = o;
+    if (t < ni) {
+      for (int b = 0; b < nb; ++b) {
+        const cplx<TI> v = alm[(size_t)(b0 + b) * nalm + idx];
+        C o;
+        o.x = (T)(g * (double)v.x);
+        o.y = m0 ? (T)0 : (T)(g * (double)v.y);
+        tile[t][b] = o;
+      }
     }
     __syncthreads();
-    for (int t = threadIdx.x; t < nl * nb; t += 256) {
-      const int l = t / nb, b = t - l * nb;
-      ALMT[(base + l) * B + b0 + b] = tile[l][b];
+    for (int q = t; q < ni * nb; q += kLayoutThreads) {
+      const int r = q / nb, b = q - r * nb;
+      ALMT[(i0 + r) * B + b0 + b] = tile[r][b];
     }
     __syncthreads();
   }
@@ -89,16 +94,16 @@ __global__ void __launch_bounds__(256)
 template <typename T, typename TO>
 hipError_t launch_alm_out(int L, int B, const cplx<T> *ALMT, cplx<TO> *alm, double f0, double fm, int acc,
                           hipStream_t st) {
-  const dim3 grid((L + 1 + kTileL - 1) / kTileL, L + 1);
-  hipLaunchKernelGGL((k_alm_out<T, TO>), grid, dim3(256), 0, st, L, B, ALMT, alm, (T)f0, (T)fm, acc);
+  const dim3 grid((unsigned)((nalm_of(L) + kLayoutThreads - 1) / kLayoutThreads));
+  hipLaunchKernelGGL((k_alm_out<T, TO>), grid, dim3(kLayoutThreads), 0, st, L, B, ALMT, alm, (T)f0, (T)fm, acc);
   return hipGetLastError();
 }
 
 template <typename T, typename TI>
 hipError_t launch_alm_in(int L, int B, const cplx<TI> *alm, const double *coefC, cplx<T> *ALMT, double s,
                          double f0, double fm, hipStream_t st) {
-  const dim3 grid((L + 1 + kTileL - 1) / kTileL, L + 1);
-  hipLaunchKernelGGL((k_alm_in<T, TI>), grid, dim3(256), 0, st, L, B, alm, coefC, ALMT, s, f0, fm);
+  const dim3 grid((unsigned)((nalm_of(L) + kLayoutThreads - 1) / kLayoutThreads));
+  hipLaunchKernelGGL((k_alm_in<T, TI>), grid, dim3(kLayoutThreads), 0, st, L, B, alm, coefC, ALMT, s, f0, fm);
   return hipGetLastError();
 }
 

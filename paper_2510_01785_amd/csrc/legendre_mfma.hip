@@ -24,6 +24,8 @@ __device__ __forceinline__ f32x16 mfma32(float a, float b, f32x16 c) {
 constexpr int kFwdWaves = 4;
 constexpr int kSubL = 64;       // l's per LDS sub-tile (two per block)
 constexpr int kTileRS = 64 + 4; // row stride of the LDS tile in floats
+constexpr int kRedRS = 32 + 1;  // row stride of the cross-wave reduction (reuses the tile)
+static_assert(kFwdWaves * kBlockL * kRedRS <= kFwdWaves * kSubL * kTileRS, "reduction fits the tile");
 
 // Analysis.  Workgroup = one (m, l0) item of the XCD-grouped block list;
 // 4 waves take 64-ring slices of every 256-ring chunk; each lane restarts its
@@ -33,7 +35,7 @@ constexpr int kTileRS = 64 + 4; // row stride of the LDS tile in floats
 // waves' partial sums are added through LDS at the end.
 __global__ void __launch_bounds__(256)
     k_legendre_fwd_mfma(Tables tb, int B, int b0, const double *__restrict__ coefA, const float2 *__restrict__ XE,
-                        const float2 *__restrict__ XO, float2 *__restrict__ ALMT) {
+                        const float2 *__restrict__ XO, float2 *__restrict__ alm, float f0, float fm, int accum) {
   __shared__ float tile[kFwdWaves * kSubL * kTileRS];
   __shared__ double sA[kBlockL];
   const int g = blockIdx.x;
@@ -147,7 +149,9 @@ __global__ void __launch_bounds__(256)
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
   }
-  // sum the four waves' partial tiles: red[w][l - l0][col]
+  // sum the four waves' partial tiles, red[w][l - l0][col] (row stride
+  // kRedRS: the reads below walk l, conflict-free), and write the caller's
+  // layout alm[b][idx(l, m)] = f_m c_lm a (Im = 0 for m = 0), or add to it
   __syncthreads();
   float *red = tile;
 #pragma unroll
@@ -157,20 +161,33 @@ __global__ void __launch_bounds__(256)
     for (int r = 0; r < 16; ++r) {
       const int i = 8 * (r >> 2) + 4 * h + (r & 3);
       const int lrel = hb * kSubL + 2 * i + par;
-      red[(w * kBlockL + lrel) * 32 + col] = acc[a][r];
+      red[(w * kBlockL + lrel) * kRedRS + col] = acc[a][r];
     }
   }
   __syncthreads();
   const double *Cn = tb.coefC + alm_idx(m, m, L) - m;
-  float *out = reinterpret_cast<float *>(ALMT);
-  for (int e = tid; e < kBlockL * 32; e += 256) {
-    const int lrel = e >> 5, cc = e & 31;
+  const size_t nalm = nalm_of(L);
+  const size_t base = alm_idx(l0, m, L);
+  const float f = (m == 0) ? f0 : fm;
+  for (int e = tid; e < 16 * kBlockL; e += 256) {
+    const int c = e / kBlockL, lrel = e % kBlockL;  // a wave walks 64 consecutive l of one channel
     const int l = l0 + lrel;
-    if (l > L || b0 + (cc >> 1) >= B) continue;
-    float s = 0.f;
+    if (l > L || b0 + c >= B) continue;
+    float re = 0.f, im = 0.f;
 #pragma unroll
-    for (int ww = 0; ww < kFwdWaves; ++ww) s += red[(ww * kBlockL + lrel) * 32 + cc];
-    out[(alm_idx(l, m, L) * B + b0) * 2 + cc] = (float)Cn[l] * s;
+    for (int ww = 0; ww < kFwdWaves; ++ww) {
+      re += red[(ww * kBlockL + lrel) * kRedRS + 2 * c];
+      im += red[(ww * kBlockL + lrel) * kRedRS + 2 * c + 1];
+    }
+    const float g = f * (float)Cn[l];
+    float2 v = make_float2(g * re, (m == 0) ? 0.f : g * im);
+    float2 *dst = alm + (size_t)(b0 + c) * nalm + base + lrel;
+    if (accum) {
+      const float2 o = *dst;
+      v.x += o.x;
+      v.y += o.y;
+    }
+    *dst = v;
   }
 }
 
@@ -336,8 +353,8 @@ __global__ void __launch_bounds__(64)
 
 bool mfma_fwd_supported(const Tables &tb) { return tb.nitems > 0; }
 
-hipError_t launch_legendre_fwd_mfma(const Tables &tb, int B, const float2 *XE, const float2 *XO, float2 *ALMT,
-                                    hipStream_t st) {
+hipError_t launch_legendre_fwd_mfma(const Tables &tb, int B, const float2 *XE, const float2 *XO, float2 *alm, double f0,
+                                    double fm, int accum, hipStream_t st) {
   // grid: 8 XCD groups x the longest group
   int longest = 0;
   {
@@ -351,7 +368,7 @@ hipError_t launch_legendre_fwd_mfma(const Tables &tb, int B, const float2 *XE, c
   }
   for (int b0 = 0; b0 < B; b0 += 16)
     hipLaunchKernelGGL(k_legendre_fwd_mfma, dim3(8 * longest), dim3(256), 0, st, tb, B, b0, tb.coefA, XE, XO,
-                       ALMT);
+                       alm, (float)f0, (float)fm, accum);
   return hipGetLastError();
 }
 

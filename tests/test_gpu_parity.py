@@ -91,7 +91,8 @@ def test_alm2map_parity(shtx, nside, lmax, batch, dtype):
 
 
 @pytest.mark.parametrize("nside,lmax,batch,dtype", [(4, 15, 2, torch.float64), (16, 47, 2, torch.float64),
-                                                    (8, 23, 3, torch.float32)])
+                                                    (8, 23, 3, torch.float32), (16, 47, 9, torch.float32),
+                                                    (32, 95, 18, torch.float32)])
 def test_backward_parity(shtx, nside, lmax, batch, dtype):
     announce("backward nside=%d lmax=%d B=%d %s" % (nside, lmax, batch, dtype))
     ct = torch.complex128 if dtype == torch.float64 else torch.complex64
