@@ -256,6 +256,8 @@ hipError_t launch_legendre_fwd_valu(const Tables &tb, int B, const cplx<T> *XE, 
       launch_fwd_cfg<T, BG, 64, 1>(tb, B, b0, XE, XO, ALMT, st);
     else if (Rp <= 1024)
       launch_fwd_cfg<T, BG, 256, 4>(tb, B, b0, XE, XO, ALMT, st);
+    else if (Rp <= 2048)
+      launch_fwd_cfg<T, BG, 1024, 2>(tb, B, b0, XE, XO, ALMT, st);
     else
       launch_fwd_cfg<T, BG, 1024, 4>(tb, B, b0, XE, XO, ALMT, st);
   }

@@ -384,7 +384,7 @@ __device__ __forceinline__ void stage_odd(cplx<T> *buf, int n, int G, int p, int
 // the power-of-two part, one radix-2 stage if needed, then one direct stage
 // per remaining odd prime factor (all <= kMaxDirectPrime on this path).
 template <typename T, int NT>
-__device__ __noinline__ void fft_mixed(cplx<T> *buf, int n, int G, int pad, const cplx<T> *__restrict__ roots) {
+__device__ __forceinline__ void fft_mixed(cplx<T> *buf, int n, int G, int pad, const cplx<T> *__restrict__ roots) {
   int rem = n, p = 1;
   while ((rem & 3) == 0) {
     stage_mix_p2<T, NT, 4>(buf, n, G, p, pad, roots);
@@ -511,7 +511,7 @@ __device__ __forceinline__ void store_pair(double2 *p, double2 a, double2 b) {
   p[1] = b;
 }
 
-constexpr int kLoadUnroll = 4;  // quads of pixels in flight per thread
+constexpr int kLoadUnroll = 2;  // quads of pixels in flight per thread
 
 template <typename TIn, typename T, int NT>
 __global__ void __launch_bounds__(NT, (sizeof(T) == 4 && NT == 512) ? 4 : 1)
@@ -609,7 +609,7 @@ __global__ void __launch_bounds__(NT, (sizeof(T) == 4 && NT == 512) ? 4 : 1)
   }
 }
 
-constexpr int kFoldUnroll = 4;  // (k, channel) items per thread with loads in flight
+constexpr int kFoldUnroll = 2;  // (k, channel) items per thread with loads in flight
 
 template <typename TOut, typename T, int NT>
 __global__ void __launch_bounds__(NT, (sizeof(T) == 4 && NT == 512) ? 4 : 1)
@@ -771,12 +771,12 @@ hipError_t launch_ring_fft_fwd(Tables tb, int B, const TIn *map, const double *w
                                cplx<T> *XO, hipStream_t st) {
   const FftGeom g = fft_geometry(tb.nside, tb.mmax_bs, B, sizeof(cplx<T>));
   const dim3 grid(fft_grid(tb.npairs, B, g.G));
-  if (g.NT == 512) {
+  if (sizeof(T) == 8 || g.NT == 512) {  // FP64 geometry always takes 512 threads
     auto kern = k_ring_fft_fwd<TIn, T, 512>;
     hipError_t e = allow_lds(kern, g.lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kern, grid, dim3(512), g.lds, st, tb, B, g.G, g.use_bs, g.tq_off, map, wtab, wscale, XE, XO);
-  } else {
+  } else if constexpr (sizeof(T) == 4) {
     auto kern = k_ring_fft_fwd<TIn, T, 1024>;
     hipError_t e = allow_lds(kern, g.lds);
     if (e != hipSuccess) return e;
@@ -791,12 +791,12 @@ hipError_t launch_ring_fft_inv(Tables tb, int B, const cplx<T> *GN, const cplx<T
                                hipStream_t st) {
   const FftGeom g = fft_geometry(tb.nside, tb.mmax_bs, B, sizeof(cplx<T>));
   const dim3 grid(fft_grid(tb.npairs, B, g.G));
-  if (g.NT == 512) {
+  if (sizeof(T) == 8 || g.NT == 512) {  // FP64 geometry always takes 512 threads
     auto kern = k_ring_fft_inv<TOut, T, 512>;
     hipError_t e = allow_lds(kern, g.lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kern, grid, dim3(512), g.lds, st, tb, B, g.G, g.use_bs, g.tq_off, GN, GS, sub, map);
-  } else {
+  } else if constexpr (sizeof(T) == 4) {
     auto kern = k_ring_fft_inv<TOut, T, 1024>;
     hipError_t e = allow_lds(kern, g.lds);
     if (e != hipSuccess) return e;

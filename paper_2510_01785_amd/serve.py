@@ -1,0 +1,301 @@
+"""Serving loop: continuous batching of mixed (nside, lmax) transform requests
+on one GPU, with admission against an HBM budget and overlap on streams.
+
+A request is one map2alm or alm2map call on a batch of channels already
+resident in device memory.  `Server.submit` queues it and returns a Future.
+An admission thread takes queued requests in arrival order; a request is
+started when a stream slot is free and its device memory (output, workspace
+and, for a new (nside, lmax), the resident tables) fits in what is left of the
+budget.  It then runs on that slot's stream and an event marks its end.  A
+completion thread resolves the futures in completion order, then returns the
+memory and the slot, which admits the next requests.
+
+* A request whose memory alone exceeds the budget is rejected at submit
+  (its future fails with `AdmissionError`); nothing is allocated.
+* A queued request can be cancelled (Future.cancel) or time out in the queue;
+  it is dropped without touching the GPU.
+* Per request the loop records arrival, admit and done times; `stats()`
+  reports p50/p99 latency, maps/s, memory in use and queue depth.
+* The budget covers what the loop allocates while a request runs (output,
+  workspace, tables of a new (nside, lmax)); a finished request's output
+  belongs to its future, i.e. to the caller.
+
+The scheduling core (`Scheduler`) is independent of the device: it drives an
+executor with `need(req)`, `launch(req, slot)`, `done(handle)` and
+`finish(handle)`.  `Server` pairs it with the GPU executor built on the C-ABI
+binding (`ops`); tests drive it with a host executor.
+"""
+import collections
+import concurrent.futures
+import threading
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+
+class AdmissionError(RuntimeError):
+    """The request needs more device memory than the whole budget."""
+
+
+@dataclass
+class Request:
+    direction: str          # "map2alm" or "alm2map"
+    nside: int
+    lmax: int
+    data: object            # device tensor: maps [B, Npix] or alm [B, nalm]
+    timeout: float = None   # seconds the request may wait in the queue
+    # filled in by the scheduler (seconds, time.perf_counter)
+    t_arrival: float = 0.0
+    t_admit: float = 0.0
+    t_done: float = 0.0
+    need: int = 0
+    future: concurrent.futures.Future = field(default_factory=concurrent.futures.Future)
+
+    @property
+    def batch(self):
+        return int(self.data.shape[0]) if getattr(self.data, "dim", lambda: 1)() > 1 else 1
+
+
+@dataclass
+class Done:
+    t_arrival: float
+    t_admit: float
+    t_done: float
+    batch: int
+    need: int
+
+
+class Scheduler:
+    """FIFO admission under a memory budget and a slot count."""
+
+    def __init__(self, executor, budget_bytes, slots, poll_s=2e-4):
+        self.ex = executor
+        self.budget = int(budget_bytes)
+        self.slots = int(slots)
+        self.poll_s = poll_s
+        self._cv = threading.Condition()
+        self._queue = collections.deque()
+        self._free_slots = list(range(self.slots))
+        self._running = {}           # slot -> (request, handle)
+        self._launching = 0          # admitted, launch in progress
+        self.in_use = 0
+        self.peak_in_use = 0
+        self.finished = []
+        self._closed = False
+        self._threads = [threading.Thread(target=self._admit_loop, daemon=True),
+                         threading.Thread(target=self._complete_loop, daemon=True)]
+        for t in self._threads:
+            t.start()
+
+    # ---------------------------------------------------------------- API
+    def submit(self, req):
+        req.t_arrival = time.perf_counter()
+        req.need = int(self.ex.need(req))
+        if req.need > self.budget:
+            req.future.set_exception(AdmissionError(
+                "request needs %d bytes, budget is %d" % (req.need, self.budget)))
+            return req.future
+        with self._cv:
+            if self._closed:
+                raise RuntimeError("scheduler closed")
+            self._queue.append(req)
+            self._cv.notify_all()
+        return req.future
+
+    def queue_depth(self):
+        with self._cv:
+            return len(self._queue)
+
+    def drain(self):
+        """Block until nothing is queued or running."""
+        with self._cv:
+            while self._queue or self._running or self._launching:
+                self._cv.wait(0.05)
+
+    def close(self):
+        self.drain()
+        with self._cv:
+            self._closed = True
+            self._cv.notify_all()
+        for t in self._threads:
+            t.join()
+
+    # ----------------------------------------------------------- threads
+    def _admit_loop(self):
+        while True:
+            with self._cv:
+                while True:
+                    if self._closed and not self._queue:
+                        return
+                    self._drop_dead_locked()
+                    if self._queue and self._free_slots and \
+                            self.in_use + self._queue[0].need <= self.budget:
+                        break
+                    self._cv.wait(0.05)
+                req = self._queue.popleft()
+                if not req.future.set_running_or_notify_cancel():
+                    continue
+                slot = self._free_slots.pop(0)
+                self.in_use += req.need
+                self.peak_in_use = max(self.peak_in_use, self.in_use)
+                req.t_admit = time.perf_counter()
+                self._launching += 1
+            try:
+                handle = self.ex.launch(req, slot)
+            except Exception as e:  # launch failed: release and report
+                with self._cv:
+                    self.in_use -= req.need
+                    self._free_slots.append(slot)
+                    self._launching -= 1
+                    self._cv.notify_all()
+                req.future.set_exception(e)
+                continue
+            with self._cv:
+                self._running[slot] = (req, handle)
+                self._launching -= 1
+                self._cv.notify_all()
+
+    def _drop_dead_locked(self):
+        """Cancelled or timed-out requests leave the queue untouched by the GPU."""
+        now = time.perf_counter()
+        keep = collections.deque()
+        for r in self._queue:
+            if r.future.cancelled():
+                continue
+            if r.timeout is not None and now - r.t_arrival > r.timeout:
+                r.future.set_exception(TimeoutError("request timed out in the queue"))
+                continue
+            keep.append(r)
+        self._queue = keep
+
+    def _complete_loop(self):
+        while True:
+            with self._cv:
+                if self._closed and not self._running and not self._queue and not self._launching:
+                    return
+                running = list(self._running.items())
+            done_any = False
+            for slot, (req, handle) in running:
+                if not self.ex.done(handle):
+                    continue
+                try:
+                    result = self.ex.finish(handle)
+                    err = None
+                except Exception as e:
+                    result, err = None, e
+                req.t_done = time.perf_counter()
+                with self._cv:
+                    del self._running[slot]
+                    self.in_use -= req.need
+                    self._free_slots.append(slot)
+                    # timing record only: the result stays with the caller's future
+                    self.finished.append(Done(req.t_arrival, req.t_admit, req.t_done, req.batch, req.need))
+                    self._cv.notify_all()
+                if err is None:
+                    req.future.set_result(result)
+                else:
+                    req.future.set_exception(err)
+                done_any = True
+            if not done_any:
+                time.sleep(self.poll_s)
+
+    # -------------------------------------------------------------- stats
+    def stats(self, t0=None, t1=None):
+        with self._cv:
+            fin = list(self.finished)
+            depth = len(self._queue)
+            in_use = self.in_use
+        if not fin:
+            return dict(requests=0, queue_depth=depth, in_use_bytes=in_use, peak_in_use_bytes=self.peak_in_use)
+        lat = np.array([r.t_done - r.t_arrival for r in fin]) * 1e3
+        wait = np.array([r.t_admit - r.t_arrival for r in fin]) * 1e3
+        t0 = min(r.t_arrival for r in fin) if t0 is None else t0
+        t1 = max(r.t_done for r in fin) if t1 is None else t1
+        maps = sum(r.batch for r in fin)
+        return dict(requests=len(fin), maps=maps, maps_per_s=maps / max(t1 - t0, 1e-12),
+                    p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
+                    queue_wait_p50_ms=float(np.percentile(wait, 50)),
+                    queue_wait_p99_ms=float(np.percentile(wait, 99)),
+                    queue_depth=depth, in_use_bytes=in_use, peak_in_use_bytes=self.peak_in_use,
+                    budget_bytes=self.budget)
+
+
+class GpuExecutor:
+    """Runs requests through the library on per-slot HIP streams."""
+
+    def __init__(self, device, slots):
+        import torch
+        from . import ops
+        self.torch, self.ops = torch, ops
+        self.device = torch.device(device)
+        self.streams = [torch.cuda.Stream(device=self.device) for _ in range(slots)]  # default priority
+        self._tables_lock = threading.Lock()
+        self._tables = set()
+
+    def _out_bytes(self, req):
+        B = req.batch
+        if req.direction == "map2alm":
+            csize = 16 if req.data.dtype == self.torch.float64 else 8
+            return B * self.ops.nalm(req.lmax) * csize
+        esize = 8 if req.data.dtype == self.torch.complex128 else 4
+        return B * self.ops.npix(req.nside) * esize
+
+    def need(self, req):
+        from . import _lib
+        if req.direction == "map2alm":
+            code = {self.torch.float64: _lib.F64, self.torch.float32: _lib.F32,
+                    self.torch.bfloat16: _lib.BF16}[req.data.dtype]
+        elif req.direction == "alm2map":
+            code = {self.torch.complex128: _lib.F64, self.torch.complex64: _lib.F32}[req.data.dtype]
+        else:
+            raise ValueError("unknown direction %r" % req.direction)
+        L = _lib.lib()
+        ws = L.shtx_workspace_bytes(req.nside, req.lmax, req.batch, code)
+        tab = 0 if (req.nside, req.lmax) in self._tables else L.shtx_tables_bytes(req.nside, req.lmax)
+        return self._out_bytes(req) + ws + tab
+
+    def launch(self, req, slot):
+        torch, ops = self.torch, self.ops
+        with self._tables_lock:
+            if (req.nside, req.lmax) not in self._tables:
+                ops.get_tables(req.nside, req.lmax, self.device)
+                torch.cuda.synchronize(self.device)  # tables ready for every stream
+                self._tables.add((req.nside, req.lmax))
+        st = self.streams[slot]
+        st.wait_stream(torch.cuda.current_stream(self.device))  # inputs written before submit
+        with torch.cuda.stream(st):
+            if req.direction == "map2alm":
+                out = ops.map2alm_raw(req.data, req.lmax)
+            else:
+                out = ops.alm2map_raw(req.data, req.nside, req.lmax)
+            ev = torch.cuda.Event()
+            ev.record(st)
+        return (ev, out)
+
+    def done(self, handle):
+        return handle[0].query()
+
+    def finish(self, handle):
+        handle[0].synchronize()
+        return handle[1]
+
+
+class Server:
+    """GPU serving loop: `submit(Request) -> Future` of the output tensor."""
+
+    def __init__(self, device="cuda:0", budget_bytes=48 << 30, slots=8):
+        self.executor = GpuExecutor(device, slots)
+        self.scheduler = Scheduler(self.executor, budget_bytes, slots)
+
+    def submit(self, req):
+        return self.scheduler.submit(req)
+
+    def stats(self, t0=None, t1=None):
+        return self.scheduler.stats(t0, t1)
+
+    def drain(self):
+        self.scheduler.drain()
+
+    def close(self):
+        self.scheduler.close()

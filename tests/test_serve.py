@@ -1,0 +1,151 @@
+"""Serving loop: admission, budget, rejection, cancellation and statistics
+with a host executor (CPU), and alone-vs-mix equality on the GPU."""
+import threading
+import time
+
+import numpy as np
+import pytest
+
+from paper_2510_01785_amd.serve import AdmissionError, Request, Scheduler
+
+
+class FakeData:
+    def __init__(self, batch):
+        self.shape = (batch, 1)
+
+    def dim(self):
+        return 2
+
+
+class HostExecutor:
+    """Each request 'runs' for dur seconds; records concurrency and memory."""
+
+    def __init__(self, dur=0.01):
+        self.dur = dur
+        self.lock = threading.Lock()
+        self.live = 0
+        self.max_live = 0
+        self.launched = []
+
+    def need(self, req):
+        return req.nside  # the tests set the byte need through nside
+
+    def launch(self, req, slot):
+        with self.lock:
+            self.live += 1
+            self.max_live = max(self.max_live, self.live)
+            self.launched.append((req.lmax, slot))
+        return [time.perf_counter() + self.dur, req]
+
+    def done(self, h):
+        return time.perf_counter() >= h[0]
+
+    def finish(self, h):
+        with self.lock:
+            self.live -= 1
+        return ("out", h[1].lmax)
+
+
+def make(need, tag, batch=1, timeout=None):
+    return Request("map2alm", need, tag, FakeData(batch), timeout=timeout)
+
+
+def test_budget_never_exceeded_and_fifo():
+    ex = HostExecutor(0.005)
+    s = Scheduler(ex, budget_bytes=100, slots=4)
+    reqs = [make(30 + (i % 3) * 20, i) for i in range(40)]
+    futs = [s.submit(r) for r in reqs]
+    for f in futs:
+        f.result(timeout=10)
+    st = s.stats()
+    s.close()
+    assert st["requests"] == 40
+    assert s.peak_in_use <= 100
+    assert ex.max_live <= 4
+    assert [t for t, _ in ex.launched] == list(range(40))  # admitted in arrival order
+    assert s.in_use == 0
+
+
+def test_over_budget_rejected_without_launch():
+    ex = HostExecutor()
+    s = Scheduler(ex, budget_bytes=100, slots=2)
+    f = s.submit(make(101, "big"))
+    with pytest.raises(AdmissionError):
+        f.result(timeout=1)
+    ok = s.submit(make(100, "fits"))
+    assert ok.result(timeout=5) == ("out", "fits")
+    s.close()
+    assert [t for t, _ in ex.launched] == ["fits"]
+
+
+def test_cancel_and_timeout_in_queue():
+    ex = HostExecutor(0.2)
+    s = Scheduler(ex, budget_bytes=10, slots=1)
+    first = s.submit(make(10, "first"))
+    time.sleep(0.02)
+    cancelled = s.submit(make(10, "cancelled"))
+    timed = s.submit(make(10, "timed", timeout=0.05))
+    last = s.submit(make(10, "last"))
+    assert cancelled.cancel()
+    assert first.result(timeout=5) == ("out", "first")
+    with pytest.raises(TimeoutError):
+        timed.result(timeout=5)
+    assert last.result(timeout=5) == ("out", "last")
+    s.close()
+    assert [t for t, _ in ex.launched] == ["first", "last"]
+
+
+def test_stats_well_formed():
+    ex = HostExecutor(0.002)
+    s = Scheduler(ex, budget_bytes=1000, slots=3)
+    rng = np.random.default_rng(17856)
+    futs = []
+    for i in range(30):
+        futs.append(s.submit(make(int(rng.integers(50, 400)), i, batch=int(rng.integers(1, 33)))))
+        time.sleep(float(rng.exponential(0.001)))
+    for f in futs:
+        f.result(timeout=10)
+    st = s.stats()
+    s.close()
+    assert st["requests"] == 30 and st["maps"] > 0
+    assert 0 < st["p50_ms"] <= st["p99_ms"]
+    assert st["queue_depth"] == 0 and st["in_use_bytes"] == 0
+    assert st["peak_in_use_bytes"] <= 1000 and st["maps_per_s"] > 0
+
+
+@pytest.mark.gpu
+def test_gpu_mix_equals_alone():
+    """Each request's output is bit-identical alone and in a concurrent mix of
+    several (nside, lmax), directions and batch sizes."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2510_01785_amd as shtx
+    from paper_2510_01785_amd import synth
+    from paper_2510_01785_amd.serve import Server
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng(17856)
+    reqs = []
+    for i in range(12):
+        nside = int(rng.choice([16, 32, 64]))
+        lmax = int(rng.choice([2 * nside - 1, 3 * nside - 1]))
+        B = int(rng.integers(1, 20))
+        if i % 2 == 0:
+            x = torch.tensor(synth.white_map(100 + i, B, 12 * nside * nside), dtype=torch.float32, device=dev)
+            reqs.append(("map2alm", nside, lmax, x))
+        else:
+            a = torch.tensor(synth.random_alm(100 + i, B, lmax), dtype=torch.complex64, device=dev)
+            reqs.append(("alm2map", nside, lmax, a))
+    alone = []
+    for d, nside, lmax, x in reqs:
+        alone.append(shtx.map2alm_raw(x, lmax) if d == "map2alm" else shtx.alm2map_raw(x, nside, lmax))
+    torch.cuda.synchronize()
+    srv = Server(dev, budget_bytes=2 << 30, slots=4)
+    futs = [srv.submit(Request(d, nside, lmax, x)) for d, nside, lmax, x in reqs]
+    outs = [f.result(timeout=60) for f in futs]
+    st = srv.stats()
+    srv.close()
+    torch.cuda.synchronize()
+    for a, o in zip(alone, outs):
+        assert torch.equal(a, o)
+    assert st["requests"] == 12 and st["peak_in_use_bytes"] <= 2 << 30
