@@ -214,9 +214,13 @@ def run_jacobi(args):
     print("[bench] jacobi nside=%d lmax=%d %s" % (nside, lmax, args.dtype), flush=True)
     a0 = torch.tensor(synth.gaussian_alm(17855, 1, lmax, "l_m2"), dtype=ct, device=dev)
     f = shtx.alm2map_raw(a0, nside, lmax).to(dt)
+    from paper_2510_01785_amd import _lib
     for _ in range(args.warmup):
         shtx.map2alm_iter(f, lmax, 3)
     torch.cuda.synchronize()
+    L = _lib.lib()
+    L.shtx_profile_reset()
+    L.shtx_profile_enable(1)
     evs = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -227,6 +231,9 @@ def run_jacobi(args):
         evs.append((e0, e1))
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    L.shtx_profile_enable(0)
+    prof = _lib.profile_read()
+    stages = {k: round(v[0] / args.steps, 3) for k, v in prof.items() if v[1]}
     lat = np.array([x.elapsed_time(y) for x, y in evs])
     err = [float((torch.linalg.vector_norm(shtx.map2alm_iter(f, lmax, k) - a0) /
                   torch.linalg.vector_norm(a0)).item()) for k in range(4)]
@@ -243,6 +250,7 @@ def run_jacobi(args):
         "dtype": args.dtype,
         "data": "synthetic",
         "rel_error_vs_input_alm_per_iteration": [float("%.3e" % e) for e in err],
+        "stages_ms_per_step": stages,
         "config": {"workload": "healpix_sht_jacobi", "nside": nside, "lmax": lmax, "batch": 1, "iterations": 3,
                    "fields": "gaussian C_l=l^-2"},
     }

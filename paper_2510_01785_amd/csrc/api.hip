@@ -151,16 +151,16 @@ constexpr int kMaxIter = 64;  // refinement iterations accepted by shtx_map2alm_
 
 int status_of(hipError_t e) { return e == hipSuccess ? SHTX_OK : SHTX_ERR_HIP; }
 
-// Matrix-core Legendre kernels serve FP32 contraction from 8 channels up
-// (below that the vector-ALU kernels are faster).  SHTX_FORCE_VALU=1 in the
+// Matrix-core Legendre kernels serve FP32 contraction from mfma_min_batch()
+// channels up (SHTX_MFMA_MIN_BATCH, default 1); SHTX_FORCE_VALU=1 in the
 // environment selects the vector-ALU kernels everywhere.
-constexpr int kMfmaMinBatch = 8;
+int mfma_min_batch() {
+  const char *e = getenv("SHTX_MFMA_MIN_BATCH");
+  return e ? atoi(e) : 1;
+}
 bool force_valu() {
-  static const bool v = [] {
-    const char *e = getenv("SHTX_FORCE_VALU");
-    return e && e[0] == '1';
-  }();
-  return v;
+  const char *e = getenv("SHTX_FORCE_VALU");
+  return e && e[0] == '1';
 }
 
 // Legendre step of the analysis.  Returns true in *direct when the kernel
@@ -176,7 +176,7 @@ template <typename T> hipError_t legendre_fwd(const Tables &tb, int B, const cpl
 template <> hipError_t legendre_fwd<float>(const Tables &tb, int B, const float2 *XE, const float2 *XO,
                                            float2 *ALMT, float2 *alm, double f0, double fm, int accum, bool *direct,
                                            hipStream_t st) {
-  *direct = B >= kMfmaMinBatch && mfma_fwd_supported(tb) && !force_valu();
+  *direct = B >= mfma_min_batch() && mfma_fwd_supported(tb) && !force_valu();
   if (*direct) return launch_legendre_fwd_mfma(tb, B, XE, XO, alm, f0, fm, accum, st);
   return launch_legendre_fwd_valu<float>(tb, B, XE, XO, ALMT, st);
 }
@@ -186,7 +186,7 @@ template <typename T> hipError_t legendre_inv(const Tables &tb, int B, const cpl
 }
 template <> hipError_t legendre_inv<float>(const Tables &tb, int B, const float2 *ALMT, SynLayout lay, float2 *GN,
                                            float2 *GS, hipStream_t st) {
-  if (B >= kMfmaMinBatch && !force_valu()) return launch_legendre_inv_mfma(tb, B, ALMT, lay, GN, GS, st);
+  if (B >= mfma_min_batch() && !force_valu()) return launch_legendre_inv_mfma(tb, B, ALMT, lay, GN, GS, st);
   return launch_legendre_inv_valu<float>(tb, B, ALMT, lay, GN, GS, st);
 }
 

@@ -26,7 +26,7 @@ constexpr int kSkipExp = -64;
 // consecutive l) item and starts every ring from a stored checkpoint of the
 // recurrence at the block start.  Checkpoints are kept for nside <= this.
 constexpr int kBlockL = 128;
-constexpr int kMaxNsideCheckpoint = 1024;
+constexpr int kMaxNsideCheckpoint = 2048;
 
 inline size_t checkpoint_items(int nside, int lmax) {
   if (nside > kMaxNsideCheckpoint) return 0;

@@ -172,59 +172,77 @@ __global__ void __launch_bounds__(NT)
       if (b0 + b < B) ALMT[alm_idx(l, m, L) * B + b0 + b] = cmk<C>(0, 0);
 }
 
-// Synthesis: grid (ring blocks, m), one ring pair per thread.  All lanes of
-// the workgroup step through the same l (from the earliest seed of the
-// block), so the a_lm of the channel group and the recurrence coefficient are
-// uniform loads; a ring joins at its seed l_s.
+// Synthesis: one wave per workgroup = (m, 64 ring pairs), one ring pair per
+// lane; every lane runs its ring's recurrence and accumulates S_e and S_o
+// for BG channels itself (no reduction).  The lanes step through l together
+// from the wave's earliest seed, 8 steps per group: seeds sit at l = m + 8j,
+// so within a group l - m is even exactly at the even steps.  The recurrence
+// coefficients and the coefficients a_l of the BG channels are wave-uniform
+// and come through scalar loads (32-bit offsets into the constant address
+// space).  Workgroups are dealt so that the 64-ring chunks of one m run on
+// one XCD.
 template <typename T, int BG>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(64)
     k_legendre_inv_valu(Tables tb, int B, int b0, const cplx<T> *__restrict__ ALMT, SynLayout lay,
                         cplx<T> *__restrict__ GN, cplx<T> *__restrict__ GS) {
   using C = cplx<T>;
-  const int m = blockIdx.y;
-  const int p = blockIdx.x * 256 + threadIdx.x;
-  const int L = tb.lmax, M = L + 1, Rp = tb.npairs;
+  typedef __attribute__((address_space(4))) const double cdouble;
+  typedef __attribute__((address_space(4))) const T creal;
+  const int L = tb.lmax, Rp = tb.npairs;
+  const int nch = (Rp + 63) / 64;
+  const int g = blockIdx.x;
+  const int x = g & 7, q = g >> 3;
+  const int m = x + 8 * (q / nch);
+  const int chunk = q % nch;
+  if (m > L) return;  // uniform
+  const int j = threadIdx.x;
+  const int p = chunk * 64 + j;
   const bool valid = p < Rp;
-  const double *A = tb.coefA + alm_idx(m, m, L) - m;
-  const cplx<T> *a = ALMT + alm_idx(m, m, L) * B - (size_t)m * B + b0;  // a[l*B + b]
   const double z = valid ? tb.rp_z[p] : 0.0;
   const int ls = valid ? tb.seed_l[(size_t)m * Rp + p] : L + 1;
   const double2 sd = valid ? tb.seed_v[(size_t)m * Rp + p] : make_double2(0.0, 0.0);
-  __shared__ int s_lmin;
-  if (threadIdx.x == 0) s_lmin = L + 1;
-  __syncthreads();
-  atomicMin(&s_lmin, ls);
-  __syncthreads();
-  const int l_begin = s_lmin;
+  int wlv = ls;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) wlv = min(wlv, __shfl_xor(wlv, o));
+  const int wl = __builtin_amdgcn_readfirstlane(wlv);
+  const int aoff = m * (2 * L + 1 - m) / 2;  // alm_idx(m, m, L) - m
+  const cdouble *A = (const cdouble *)tb.coefA + aoff;
+  // a[l][b] (re, im) of this channel group: T index (aoff + l) * 2B + 2(b0 + b) + {0, 1}
+  const creal *a = (const creal *)ALMT + (size_t)aoff * 2 * B + 2 * b0;
+  const int arow = 2 * B;
   T se[BG][2], so[BG][2];
 #pragma unroll
   for (int b = 0; b < BG; ++b) se[b][0] = se[b][1] = so[b][0] = so[b][1] = (T)0;
   double prv = 0.0, cur = 0.0;
-  for (int l0 = l_begin; l0 <= L; l0 += kChunk) {
-    const bool active = ls <= l0 + kChunk - 1;
+#pragma unroll 1
+  for (int lq = wl; lq <= L; lq += 8) {
+    T lam[8];
 #pragma unroll
-    for (int c = 0; c < kChunk; ++c) {
-      const int l = l0 + c;
-      if (l > L) break;
-      if (l == ls) {
-        prv = sd.x;
-        cur = sd.y;
+    for (int u = 0; u < 8; ++u) {
+      const double nx = fma(A[lq + u] * z, cur, -prv);  // coefficients padded past lmax (unused values)
+      if (u == 0) {
+        const bool inj = (lq == ls);
+        prv = inj ? sd.x : cur;
+        cur = inj ? sd.y : nx;
       } else {
-        const double nx = fma(A[l] * z, cur, -prv);
         prv = cur;
         cur = nx;
       }
-      const T mu = active ? (T)cur : (T)0;
-      const bool odd = (l - m) & 1;
+      lam[u] = (T)cur;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      if (lq + u > L) break;  // last group: rows past lmax (padding) are not read
+      const creal *row = a + (size_t)(lq + u) * arow;
 #pragma unroll
       for (int b = 0; b < BG; ++b) {
-        const C v = (b0 + b < B) ? a[(size_t)l * B + b] : cmk<C>(0, 0);
-        if (odd) {
-          so[b][0] += mu * v.x;
-          so[b][1] += mu * v.y;
+        const T ar = row[2 * b], ai = row[2 * b + 1];
+        if (u & 1) {
+          so[b][0] = fma(lam[u], ar, so[b][0]);
+          so[b][1] = fma(lam[u], ai, so[b][1]);
         } else {
-          se[b][0] += mu * v.x;
-          se[b][1] += mu * v.y;
+          se[b][0] = fma(lam[u], ar, se[b][0]);
+          se[b][1] = fma(lam[u], ai, se[b][1]);
         }
       }
     }
@@ -264,13 +282,28 @@ hipError_t launch_legendre_fwd_valu(const Tables &tb, int B, const cplx<T> *XE, 
   return hipGetLastError();
 }
 
+template <typename T, int BG>
+static void launch_inv_cfg(const Tables &tb, int B, int b0, const cplx<T> *ALMT, SynLayout lay, cplx<T> *GN,
+                           cplx<T> *GS, hipStream_t st) {
+  const int nch = (tb.npairs + 63) / 64;
+  const int nm = (tb.lmax + 1 + 7) / 8;
+  hipLaunchKernelGGL((k_legendre_inv_valu<T, BG>), dim3(8 * nm * nch), dim3(64), 0, st, tb, B, b0, ALMT, lay, GN,
+                     GS);
+}
+
+// Channel groups of 4 (FP32) or 2 (FP64), then 2 and 1 for the rest: the
+// recurrence is shared by a group, the groups' channels are never padding.
 template <typename T>
 hipError_t launch_legendre_inv_valu(const Tables &tb, int B, const cplx<T> *ALMT, SynLayout lay, cplx<T> *GN,
                                     cplx<T> *GS, hipStream_t st) {
-  constexpr int BG = sizeof(T) == 8 ? 2 : 4;
-  const dim3 grid((tb.npairs + 255) / 256, tb.lmax + 1);
-  for (int b0 = 0; b0 < B; b0 += BG)
-    hipLaunchKernelGGL((k_legendre_inv_valu<T, BG>), grid, dim3(256), 0, st, tb, B, b0, ALMT, lay, GN, GS);
+  constexpr int BGMAX = sizeof(T) == 8 ? 2 : 4;
+  int b0 = 0;
+  for (; b0 + BGMAX <= B; b0 += BGMAX) launch_inv_cfg<T, BGMAX>(tb, B, b0, ALMT, lay, GN, GS, st);
+  if (BGMAX == 4 && b0 + 2 <= B) {
+    launch_inv_cfg<T, 2>(tb, B, b0, ALMT, lay, GN, GS, st);
+    b0 += 2;
+  }
+  if (b0 < B) launch_inv_cfg<T, 1>(tb, B, b0, ALMT, lay, GN, GS, st);
   return hipGetLastError();
 }
 

@@ -137,12 +137,14 @@ def test_bf16_input_map2alm(shtx):
     assert rel_l2(got.cpu().numpy(), ref) <= 1e-5
 
 
-@pytest.mark.parametrize("nside,lmax,batch", [(32, 95, 16), (64, 255, 20)])
-def test_mfma_matches_valu_path(shtx, nside, lmax, batch, monkeypatch):
-    """The matrix-core and vector-ALU Legendre kernels agree to FP32 rounding
-    (the latter selected with SHTX_FORCE_VALU in a child process would be
-    cleaner; here both are compared with the oracle instead)."""
-    announce("mfma vs oracle nside=%d lmax=%d B=%d" % (nside, lmax, batch))
+@pytest.mark.parametrize("nside,lmax,batch,force_valu", [(32, 95, 16, "0"), (64, 255, 20, "0"), (32, 95, 7, "1"),
+                                                         (64, 191, 1, "1"), (16, 47, 3, "0")])
+def test_fp32_legendre_paths(shtx, nside, lmax, batch, force_valu, monkeypatch):
+    """FP32 through the matrix-core Legendre kernels (default) and through the
+    vector-ALU kernels (SHTX_FORCE_VALU=1, read by the library per call), each
+    against the oracle."""
+    monkeypatch.setenv("SHTX_FORCE_VALU", force_valu)
+    announce("fp32 legendre path valu=%s nside=%d lmax=%d B=%d" % (force_valu, nside, lmax, batch))
     f = synth.white_map(99, batch, geometry.npix(nside))
     x = torch.tensor(f, dtype=torch.float32, device="cuda")
     ref = sht.map2alm(x.double().cpu().numpy(), lmax, nside)
