@@ -58,7 +58,6 @@ def parse():
 STAGE_KERNEL = {  # stage -> (kernel symbol, source file)
     "ring_fft_fwd": ("k_ring_fft_fwd", "ring_fft.hip"),
     "legendre_fwd": ("k_legendre_fwd_mfma", "legendre_mfma.hip"),
-    "alm_out": ("k_alm_out", "layout.hip"),
     "alm_in": ("k_alm_in", "layout.hip"),
     "legendre_inv": ("k_legendre_inv_mfma", "legendre_mfma.hip"),
     "ring_fft_inv": ("k_ring_fft_inv", "ring_fft.hip"),
@@ -345,7 +344,6 @@ def main():
         "legendre_inv": (leg_bound, 4.0 * executed * B, "TFLOP/s"),
         "ring_fft_fwd": ("hbm", float(npix * B * esize + spec_bytes), "GB/s"),
         "ring_fft_inv": ("hbm", float(npix * B * esize + spec_bytes), "GB/s"),
-        "alm_out": ("hbm", 2.0 * alm_bytes, "GB/s"),
         "alm_in": ("hbm", 2.0 * alm_bytes, "GB/s"),
     }
     bound, amount, unit = work[dom]

@@ -13,7 +13,7 @@ EXPORTS = ("shtx_version", "shtx_status_string", "shtx_tables_bytes", "shtx_tabl
            "shtx_map2alm_backward", "shtx_alm2map_backward", "shtx_iter_workspace_bytes",
            "shtx_map2alm_iter", "shtx_profile_enable",
            "shtx_profile_reset", "shtx_profile_read", "shtx_stage_name")
-STAGES = ("ring_fft_fwd", "legendre_fwd", "alm_out", "alm_in", "legendre_inv", "ring_fft_inv")
+STAGES = ("ring_fft_fwd", "legendre_fwd", "alm_in", "legendre_inv", "ring_fft_inv")
 
 _lib = None
 

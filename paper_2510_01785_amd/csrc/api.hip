@@ -19,7 +19,8 @@ hipError_t launch_ring_fft_fwd(Tables, int, const TIn *, const double *, double,
 template <typename TOut, typename T>
 hipError_t launch_ring_fft_inv(Tables, int, const cplx<T> *, const cplx<T> *, const TOut *, TOut *, hipStream_t);
 template <typename T>
-hipError_t launch_legendre_fwd_valu(const Tables &, int, const cplx<T> *, const cplx<T> *, cplx<T> *, hipStream_t);
+hipError_t launch_legendre_fwd_valu(const Tables &, int, const cplx<T> *, const cplx<T> *, cplx<T> *, double, double,
+                                    int, hipStream_t);
 template <typename T>
 hipError_t launch_legendre_inv_valu(const Tables &, int, const cplx<T> *, SynLayout, cplx<T> *, cplx<T> *,
                                     hipStream_t);
@@ -27,8 +28,6 @@ bool mfma_fwd_supported(const Tables &tb);
 hipError_t launch_legendre_fwd_mfma(const Tables &, int, const float2 *, const float2 *, float2 *, double, double, int,
                                     hipStream_t);
 hipError_t launch_legendre_inv_mfma(const Tables &, int, const float2 *, SynLayout, float2 *, float2 *, hipStream_t);
-template <typename T, typename TO>
-hipError_t launch_alm_out(int, int, const cplx<T> *, cplx<TO> *, double, double, int, hipStream_t);
 template <typename T, typename TI>
 hipError_t launch_alm_in(int, int, const cplx<TI> *, const double *, cplx<T> *, double, double, double,
                          hipStream_t);
@@ -36,9 +35,9 @@ hipError_t launch_alm_in(int, int, const cplx<TI> *, const double *, cplx<T> *, 
 namespace {
 
 // ------------------------------------------------------------ stage timing
-enum Stage { kStFftFwd = 0, kStLegFwd, kStAlmOut, kStAlmIn, kStLegInv, kStFftInv, kNumStages };
-const char *kStageNames[kNumStages] = {"ring_fft_fwd", "legendre_fwd", "alm_out",
-                                       "alm_in",       "legendre_inv", "ring_fft_inv"};
+enum Stage { kStFftFwd = 0, kStLegFwd, kStAlmIn, kStLegInv, kStFftInv, kNumStages };
+const char *kStageNames[kNumStages] = {"ring_fft_fwd", "legendre_fwd", "alm_in", "legendre_inv",
+                                       "ring_fft_inv"};
 
 struct Profiler {
   std::mutex mu;
@@ -152,33 +151,30 @@ constexpr int kMaxIter = 64;  // refinement iterations accepted by shtx_map2alm_
 int status_of(hipError_t e) { return e == hipSuccess ? SHTX_OK : SHTX_ERR_HIP; }
 
 // Matrix-core Legendre kernels serve FP32 contraction from mfma_min_batch()
-// channels up (SHTX_MFMA_MIN_BATCH, default 1); SHTX_FORCE_VALU=1 in the
-// environment selects the vector-ALU kernels everywhere.
+// channels up (SHTX_MFMA_MIN_BATCH, default 5: below that the 32-column
+// matrix tiles are mostly padding and the vector-ALU kernels are faster);
+// SHTX_FORCE_VALU=1 in the environment selects the vector-ALU kernels
+// everywhere.  Both are read per call.
 int mfma_min_batch() {
   const char *e = getenv("SHTX_MFMA_MIN_BATCH");
-  return e ? atoi(e) : 1;
+  return e ? atoi(e) : 5;
 }
 bool force_valu() {
   const char *e = getenv("SHTX_FORCE_VALU");
   return e && e[0] == '1';
 }
 
-// Legendre step of the analysis.  Returns true in *direct when the kernel
-// wrote the caller's layout itself (matrix-core path: factors f0 / fm and the
-// accumulate mode applied in its epilogue); otherwise the coefficients are in
-// ALMT for k_alm_out.
+// Legendre step of the analysis; both kernels write the caller's layout
+// themselves (factors f0 / fm, optional accumulation).
 template <typename T> hipError_t legendre_fwd(const Tables &tb, int B, const cplx<T> *XE, const cplx<T> *XO,
-                                              cplx<T> *ALMT, cplx<T> *, double, double, int, bool *direct,
-                                              hipStream_t st) {
-  *direct = false;
-  return launch_legendre_fwd_valu<T>(tb, B, XE, XO, ALMT, st);
+                                              cplx<T> *alm, double f0, double fm, int accum, hipStream_t st) {
+  return launch_legendre_fwd_valu<T>(tb, B, XE, XO, alm, f0, fm, accum, st);
 }
-template <> hipError_t legendre_fwd<float>(const Tables &tb, int B, const float2 *XE, const float2 *XO,
-                                           float2 *ALMT, float2 *alm, double f0, double fm, int accum, bool *direct,
-                                           hipStream_t st) {
-  *direct = B >= mfma_min_batch() && mfma_fwd_supported(tb) && !force_valu();
-  if (*direct) return launch_legendre_fwd_mfma(tb, B, XE, XO, alm, f0, fm, accum, st);
-  return launch_legendre_fwd_valu<float>(tb, B, XE, XO, ALMT, st);
+template <> hipError_t legendre_fwd<float>(const Tables &tb, int B, const float2 *XE, const float2 *XO, float2 *alm,
+                                           double f0, double fm, int accum, hipStream_t st) {
+  if (B >= mfma_min_batch() && mfma_fwd_supported(tb) && !force_valu())
+    return launch_legendre_fwd_mfma(tb, B, XE, XO, alm, f0, fm, accum, st);
+  return launch_legendre_fwd_valu<float>(tb, B, XE, XO, alm, f0, fm, accum, st);
 }
 template <typename T> hipError_t legendre_inv(const Tables &tb, int B, const cplx<T> *ALMT, SynLayout lay,
                                               cplx<T> *GN, cplx<T> *GS, hipStream_t st) {
@@ -201,15 +197,8 @@ int run_analysis(const Tables &tb, int B, const TIn *map, cplx<T> *alm, const do
     e = launch_ring_fft_fwd<TIn, T>(tb, B, map, wtab, wscale, w.specA, w.specB, st);
   }
   if (e != hipSuccess) return SHTX_ERR_HIP;
-  bool direct = false;
-  {
-    StageTimer t(kStLegFwd, st);
-    e = legendre_fwd<T>(tb, B, w.specA, w.specB, w.almt, alm, f0, fm, accumulate, &direct, st);
-  }
-  if (e != hipSuccess) return SHTX_ERR_HIP;
-  if (direct) return SHTX_OK;
-  StageTimer t(kStAlmOut, st);
-  return status_of(launch_alm_out<T, T>(tb.lmax, B, w.almt, alm, f0, fm, accumulate, st));
+  StageTimer t(kStLegFwd, st);
+  return status_of(legendre_fwd<T>(tb, B, w.specA, w.specB, alm, f0, fm, accumulate, st));
 }
 
 // synthesis chain: caller layout with factors -> Legendre -> ring FFT

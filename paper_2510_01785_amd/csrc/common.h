@@ -115,13 +115,17 @@ inline SynLayout syn_layout(int nside, int lmax, int mmax_bs, int batch, size_t 
 // groups of 8 coefficients without clamping at lmax; the values loaded past
 // lmax only meet masked terms).
 constexpr size_t kCoefPad = 8;
+// Zero doubles after the last recurrence coefficient in the table buffer: the
+// analysis kernels load the coefficients of a whole 128-l block without
+// clamping at lmax (rows past lmax are never stored).
+constexpr size_t kCoefPadTable = kBlockL;
 
 // Byte offsets of the pieces of the resident table buffer.
 struct TableOffsets {
   size_t rp_n, rp_sN, rp_sS, rp_p0n, rp_p0d;  // int32 [Rp]
   size_t rp_M, rp_bsoff;                      // int32 [Rp]: Bluestein length (0: mixed radix), offset
   size_t rp_z, rp_sth, rp_w;                  // double [Rp]
-  size_t coefA, coefC;                        // double [nalm + kCoefPad]
+  size_t coefA, coefC;                        // double [nalm + kCoefPadTable], zero padding
   size_t seed_l;                              // int32 [(L+1) * Rp]
   size_t seed_v;                              // double2 [(L+1) * Rp]
   size_t roots64;                             // double2 [2N(N+1)]  per ring length 4i
@@ -164,8 +168,8 @@ inline TableOffsets table_offsets(int nside, int lmax) {
   o.rp_z = take(Rp * 8);
   o.rp_sth = take(Rp * 8);
   o.rp_w = take(Rp * 8);
-  o.coefA = take((nalm + kCoefPad) * 8);
-  o.coefC = take((nalm + kCoefPad) * 8);
+  o.coefA = take((nalm + kCoefPadTable) * 8);
+  o.coefC = take((nalm + kCoefPadTable) * 8);
   o.seed_l = take((size_t)(lmax + 1) * Rp * 4);
   o.seed_v = take((size_t)(lmax + 1) * Rp * 16);
   o.roots64 = take(nroots * 16);

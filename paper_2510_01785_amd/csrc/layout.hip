@@ -1,62 +1,21 @@
-// Conversions between the caller's coefficient layout alm[b][idx(l,m)] and
-// the transposed internal layout ALMT[idx(l,m)][b] of the Legendre kernels,
-// with the per-coefficient scale factors of each entry point.
+// Conversion of the caller's coefficient layout alm[b][idx(l,m)] into the
+// transposed internal layout ALMT[idx(l,m)][b] of the synthesis Legendre
+// kernels, with the per-coefficient scale factors of each entry point:
 //
-//   to caller:   alm = f_m * ALMT           (Im of m = 0 set to 0),
-//                or alm += f_m * ALMT       (accumulating, iterative refinement)
-//   from caller: ALMT = s * f_m * c_lm * alm (Im of m = 0 ignored)
+//   ALMT = s * f_m * c_lm * alm   (Im of m = 0 ignored)
 //
 // f_m is f0 for m = 0 and fm for m > 0; c_lm is the normalisation of the
 // scaled recurrence (tables.hip) that the synthesis kernels expect folded in.
+// (The analysis kernels write the caller's layout themselves.)
 #include "common.h"
 
 namespace shtx {
 
 // A workgroup takes kLayoutThreads consecutive coefficient indices idx(l, m)
 // (m = 0 exactly for idx <= lmax) and 16 channels at a time, through an LDS
-// tile: the caller side alm[b][idx] is read / written along idx and the
-// internal side ALMT[idx][b] as one contiguous run, both coalesced.
+// tile: the caller side alm[b][idx] is read along idx and the internal side
+// ALMT[idx][b] written as one contiguous run, both coalesced.
 constexpr int kLayoutThreads = 256;
-
-template <typename T, typename TO>
-__global__ void __launch_bounds__(kLayoutThreads)
-    k_alm_out(int L, int B, const cplx<T> *__restrict__ ALMT, cplx<TO> *__restrict__ alm, T f0, T fm, int acc) {
-  using C = cplx<T>;
-  using CO = cplx<TO>;
-  __shared__ C tile[kLayoutThreads][17];
-  const size_t nalm = nalm_of(L);
-  const size_t i0 = (size_t)blockIdx.x * kLayoutThreads;
-  const int ni = (int)min((size_t)kLayoutThreads, nalm - i0);
-  const int t = threadIdx.x;
-  const size_t idx = i0 + t;
-  const bool m0 = idx <= (size_t)L;
-  const T f = m0 ? f0 : fm;
-  for (int b0 = 0; b0 < B; b0 += 16) {
-    const int nb = min(16, B - b0);
-    // ALMT rows i0..i0+ni-1, channels b0..b0+nb-1: one contiguous run per row
-    for (int q = t; q < ni * nb; q += kLayoutThreads) {
-      const int r = q / nb, b = q - r * nb;
-      tile[r][b] = ALMT[(i0 + r) * B + b0 + b];
-    }
-    __syncthreads();
-    if (t < ni) {
-      for (int b = 0; b < nb; ++b) {
-        const C v = tile[t][b];
-        CO o;
-        o.x = (TO)(f * v.x);
-        o.y = m0 ? (TO)0 : (TO)(f * v.y);
-        CO *dst = alm + (size_t)(b0 + b) * nalm + idx;
-        if (acc) {
-          const CO prev = *dst;
-          o.x += prev.x;
-          o.y += prev.y;
-        }
-        *dst = o;
-      }
-    }
-    __syncthreads();
-  }
-}
 
 template <typename T, typename TI>
 __global__ void __launch_bounds__(kLayoutThreads)
@@ -91,14 +50,6 @@ __global__ void __launch_bounds__(kLayoutThreads)
   }
 }
 
-template <typename T, typename TO>
-hipError_t launch_alm_out(int L, int B, const cplx<T> *ALMT, cplx<TO> *alm, double f0, double fm, int acc,
-                          hipStream_t st) {
-  const dim3 grid((unsigned)((nalm_of(L) + kLayoutThreads - 1) / kLayoutThreads));
-  hipLaunchKernelGGL((k_alm_out<T, TO>), grid, dim3(kLayoutThreads), 0, st, L, B, ALMT, alm, (T)f0, (T)fm, acc);
-  return hipGetLastError();
-}
-
 template <typename T, typename TI>
 hipError_t launch_alm_in(int L, int B, const cplx<TI> *alm, const double *coefC, cplx<T> *ALMT, double s,
                          double f0, double fm, hipStream_t st) {
@@ -107,10 +58,6 @@ hipError_t launch_alm_in(int L, int B, const cplx<TI> *alm, const double *coefC,
   return hipGetLastError();
 }
 
-template hipError_t launch_alm_out<double, double>(int, int, const double2 *, double2 *, double, double, int,
-                                                   hipStream_t);
-template hipError_t launch_alm_out<float, float>(int, int, const float2 *, float2 *, double, double, int,
-                                                 hipStream_t);
 template hipError_t launch_alm_in<double, double>(int, int, const double2 *, const double *, double2 *, double,
                                                   double, double, hipStream_t);
 template hipError_t launch_alm_in<float, float>(int, int, const float2 *, const double *, float2 *, double, double,

@@ -9,167 +9,187 @@
 // These kernels serve any batch size and both FP64 and FP32 contraction.
 // Each ring starts at its stored seed l_s (a multiple of 8 above m, below
 // which |lambda_lm| < 2^-64) and runs to lmax.
+#include <algorithm>
+
 #include "common.h"
 
 namespace shtx {
 
-constexpr int kChunk = kAlign;  // l values per reduction round (8)
+// Analysis: a workgroup takes one (m, 128-l block) item of the XCD-grouped
+// item list and starts every ring from its stored recurrence checkpoint at
+// the block start (as the matrix-core kernel does).  Each lane owns R ring
+// pairs of its wave's slice (rings j, j + 64, ...), runs their recurrences
+// and, per step l, sums lambda_lm(z) X over them for BG channels (X = E for
+// even l - m, O for odd: item starts are m + 128 k).  Every SL steps the wave
+// transposes these per-lane sums through a wave-private LDS tile [slot][lane]
+// (slot = (step, channel)); lane (slot, h) then adds the values of 64/H ring
+// lanes into its accumulator of that slot.  At the end the 4 waves x H
+// partial sums of every (l, channel) are added through LDS, scaled by c_lm
+// and the entry point's factor, and written (or added) to the caller's layout
+// alm[b][idx(l, m)], Im = 0 for m = 0.
+template <typename T> struct FwdValuShape {
+  static constexpr int kSlots = sizeof(T) == 8 ? 16 : 32;  // (step, channel) slots per transpose
+  static constexpr int kRS = 65;                           // tile row stride in complex elements
+};
 
-// Sum over the 64 lanes of a wave of 8 per-lane values v[0..7]; afterwards
-// lane L holds the total of v[(L>>5&1)*4 + (L>>4&1)*2 + (L>>3&1)].
-template <typename T> __device__ __forceinline__ T wave_reduce_scatter8(const T (&v)[8]) {
-  const int lane = threadIdx.x & 63;
-  const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8;
-  T w[4];
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const T send = b5 ? v[q] : v[q + 4];
-    const T keep = b5 ? v[q + 4] : v[q];
-    w[q] = keep + __shfl_xor(send, 32);
-  }
-  T u[2];
-#pragma unroll
-  for (int q = 0; q < 2; ++q) {
-    const T send = b4 ? w[q] : w[q + 2];
-    const T keep = b4 ? w[q + 2] : w[q];
-    u[q] = keep + __shfl_xor(send, 16);
-  }
-  T t = (b3 ? u[1] : u[0]) + __shfl_xor(b3 ? u[0] : u[1], 8);
-  t += __shfl_xor(t, 4);
-  t += __shfl_xor(t, 2);
-  t += __shfl_xor(t, 1);
-  return t;
-}
-
-// Analysis: one workgroup per m (balanced order: m = blockIdx.x gives the
-// longest rows first), NT threads, each owning up to RPT ring pairs
-// p = tid + NT*j, with the pair's E/O spectra for BG channels in registers.
-// Per chunk of 8 l's every lane accumulates its rings' contributions, the
-// wave reduces them with a reduce-scatter, and the waves' totals are summed
-// through LDS.  Output: ALMT[idx(l,m)][b] = c_lm * sum_p mu_lm(p) X(p).
-template <typename T, int BG, int NT, int RPT>
-__global__ void __launch_bounds__(NT)
-    k_legendre_fwd_valu(Tables tb, int B, int b0, const cplx<T> *__restrict__ XE,
-                        const cplx<T> *__restrict__ XO, cplx<T> *__restrict__ ALMT) {
+template <typename T, int BG, int R>
+__global__ void __launch_bounds__(256)
+    k_legendre_fwd_valu(Tables tb, int B, int b0, const cplx<T> *__restrict__ XE, const cplx<T> *__restrict__ XO,
+                        cplx<T> *__restrict__ alm, T f0, T fm, int accum) {
   using C = cplx<T>;
-  constexpr int NW = NT / 64;
-  __shared__ C red[2][kChunk][BG][NW];
-  const int m = blockIdx.x;
-  const int L = tb.lmax, M = L + 1, Rp = tb.npairs;
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const double *A = tb.coefA + alm_idx(m, m, L) - m;
-  const double *Cn = tb.coefC + alm_idx(m, m, L) - m;
+  typedef __attribute__((address_space(4))) const double cdouble;
+  constexpr int NW = 4;
+  constexpr int SLOTS = FwdValuShape<T>::kSlots, RS = FwdValuShape<T>::kRS;
+  constexpr int SL = SLOTS / BG;     // steps per transpose
+  constexpr int H = 64 / SLOTS;      // lane groups that share a slot
+  constexpr int NG = kBlockL / SL;   // transposes per block
+  constexpr int LPH = 64 / H;        // ring lanes summed by one lane
+  static_assert(SL % 2 == 0 && kBlockL % SL == 0, "steps per transpose");
+  static_assert(NW * H * kBlockL * BG <= NW * SLOTS * RS, "final reduction fits the tile");
+  __shared__ C tile[NW * SLOTS * RS];
 
-  double z[RPT], prv[RPT], cur[RPT];
-  int ls[RPT];
-  double2 sd[RPT];
-  C xe[RPT][BG], xo[RPT][BG];
-  int lmin = L + 1;
+  const int g = blockIdx.x;
+  const int x = g & 7, k = g >> 3;
+  const int i0 = tb.ck_xoff[x];
+  if (k >= tb.ck_xoff[x + 1] - i0) return;  // uniform across the workgroup
+  const int item = i0 + k;
+  const int2 it = tb.ck_items[item];
+  const int m = it.x, l0 = it.y;
+  const int L = tb.lmax, M = L + 1, Rp = tb.npairs;
+  const int tid = threadIdx.x, w = __builtin_amdgcn_readfirstlane(tid >> 6), j = tid & 63;
+  const int slot = j % SLOTS, h = j / SLOTS;
+  const int aoff = m * (2 * L + 1 - m) / 2;  // alm_idx(m, m, L) - m
+  const int ng_end = min(NG, (L - l0) / SL + 1);  // transposes that hold a row l <= lmax
+  C *tw = tile + w * SLOTS * RS;
+
+  C acc[NG];
 #pragma unroll
-  for (int j = 0; j < RPT; ++j) {
-    const int p = tid + NT * j;
-    prv[j] = 0.0;
-    cur[j] = 0.0;
-    if (p < Rp) {
-      z[j] = tb.rp_z[p];
-      ls[j] = tb.seed_l[(size_t)m * Rp + p];
-      sd[j] = tb.seed_v[(size_t)m * Rp + p];
+  for (int q = 0; q < NG; ++q) acc[q] = cmk<C>(0, 0);
+
+  for (int c0 = w * 64 * R; c0 < Rp; c0 += NW * 64 * R) {
+    int t0[R];
+    int tmin = kBlockL;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int q = c0 + r * 64 + j;
+      t0[r] = q < Rp ? (int)tb.ck_t[(size_t)item * Rp + q] : kBlockL;
+      tmin = min(tmin, t0[r]);
+    }
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) tmin = min(tmin, __shfl_xor(tmin, o));
+    const int g_begin = __builtin_amdgcn_readfirstlane(tmin) / SL;  // earlier transposes hold zeros only
+    if (g_begin >= ng_end) continue;                                 // uniform: no ring of this slice is active
+    double z[R], prv[R], cur[R];
+    double2 v[R];
+    C xe[R][BG], xo[R][BG];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int q = c0 + r * 64 + j;
+      const bool ok = q < Rp;
+      const int qc = ok ? q : Rp - 1;  // idle lanes read finite data; their lambda stays zero
+      z[r] = tb.rp_z[qc];
+      v[r] = ok ? tb.ck_v[(size_t)item * Rp + q] : make_double2(0.0, 0.0);
+      prv[r] = cur[r] = 0.0;
+      const size_t o = ((size_t)qc * M + m) * B + b0;
 #pragma unroll
       for (int b = 0; b < BG; ++b) {
-        const bool ok = (b0 + b) < B;
-        const size_t o = ((size_t)p * M + m) * B + b0 + b;
-        xe[j][b] = ok ? XE[o] : cmk<C>(0, 0);
-        xo[j][b] = ok ? XO[o] : cmk<C>(0, 0);
+        xe[r][b] = XE[o + b];
+        xo[r][b] = XO[o + b];
       }
-    } else {
-      z[j] = 0.0;
-      ls[j] = L + 1;
-      sd[j] = make_double2(0.0, 0.0);
-#pragma unroll
-      for (int b = 0; b < BG; ++b) xe[j][b] = xo[j][b] = cmk<C>(0, 0);
     }
-    lmin = min(lmin, ls[j]);
-  }
-  // first chunk any ring of the workgroup needs
-  __shared__ int s_lmin;
-  if (tid == 0) s_lmin = L + 1;
-  __syncthreads();
-  atomicMin(&s_lmin, lmin);
-  __syncthreads();
-  const int l_begin = s_lmin;
-
-  int buf = 0;
-  for (int l0 = l_begin; l0 <= L; l0 += kChunk) {
-    T acc[kChunk][BG][2];
+    double a8[8];
 #pragma unroll
-    for (int c = 0; c < kChunk; ++c)
+    for (int q = 0; q < NG; ++q) {
+      if (q < g_begin || q >= ng_end) continue;  // uniform
 #pragma unroll
-      for (int b = 0; b < BG; ++b) acc[c][b][0] = acc[c][b][1] = (T)0;
+      for (int u = 0; u < SL; ++u) {
+        const int t = q * SL + u;
+        if (u % 8 == 0) {
+          // 8 coefficients per scalar load; the opaque offset keeps the loads
+          // of later groups from being hoisted (SGPR pressure).  Past lmax
+          // the table's zero padding is read (rows that are never stored).
+          int ao = aoff + l0 + t;
+          asm volatile("" : "+s"(ao));
 #pragma unroll
-    for (int j = 0; j < RPT; ++j) {
-      if (ls[j] > l0 + kChunk - 1) continue;  // not started within this chunk
-#pragma unroll
-      for (int c = 0; c < kChunk; ++c) {
-        const int l = l0 + c;
-        if (l > L) break;
-        if (l == ls[j]) {
-          prv[j] = sd[j].x;
-          cur[j] = sd[j].y;
-        } else if (l > ls[j]) {
-          const double nx = fma(A[l] * z[j], cur[j], -prv[j]);
-          prv[j] = cur[j];
-          cur[j] = nx;
-        } else {
-          continue;
+          for (int i = 0; i < 8; ++i) a8[i] = ((const cdouble *)tb.coefA)[ao + i];
         }
-        const T mu = (T)cur[j];
-        const bool odd = (l - m) & 1;
+        const double a = a8[u % 8];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const double nx = fma(a * z[r], cur[r], -prv[r]);
+          if (t % kAlign == 0) {
+            const bool inj = (t == t0[r]);
+            prv[r] = inj ? v[r].x : cur[r];
+            cur[r] = inj ? v[r].y : nx;
+          } else {
+            prv[r] = cur[r];
+            cur[r] = nx;
+          }
+        }
 #pragma unroll
         for (int b = 0; b < BG; ++b) {
-          const C x = odd ? xo[j][b] : xe[j][b];
-          acc[c][b][0] += mu * x.x;
-          acc[c][b][1] += mu * x.y;
+          T sr = 0, si = 0;
+#pragma unroll
+          for (int r = 0; r < R; ++r) {
+            const T lam = (T)cur[r];
+            const C xv = (u & 1) ? xo[r][b] : xe[r][b];
+            sr = fma(lam, xv.x, sr);
+            si = fma(lam, xv.y, si);
+          }
+          tw[(u * BG + b) * RS + j] = cmk<C>(sr, si);
         }
       }
-    }
-    // reduce each (b, re/im) over the wave, 8 l's at a time
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      const C *src = tw + slot * RS + h * LPH;
+      T sr = 0, si = 0;
 #pragma unroll
-    for (int b = 0; b < BG; ++b) {
-      T vr[kChunk], vi[kChunk];
-#pragma unroll
-      for (int c = 0; c < kChunk; ++c) {
-        vr[c] = acc[c][b][0];
-        vi[c] = acc[c][b][1];
+      for (int i = 0; i < LPH; ++i) {
+        const C e = src[i];
+        sr += e.x;
+        si += e.y;
       }
-      const T sr = wave_reduce_scatter8<T>(vr);
-      const T si = wave_reduce_scatter8<T>(vi);
-      if ((lane & 7) == 0) {
-        const int c = ((lane >> 5) & 1) * 4 + ((lane >> 4) & 1) * 2 + ((lane >> 3) & 1);
-        red[buf][c][b][wave] = cmk<C>(sr, si);
-      }
+      acc[q].x += sr;
+      acc[q].y += si;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
-    __syncthreads();
-    if (tid < kChunk * BG) {
-      const int c = tid / BG, b = tid - c * BG;
-      const int l = l0 + c;
-      if (l <= L && b0 + b < B) {
-        T sr = 0, si = 0;
-#pragma unroll
-        for (int w = 0; w < NW; ++w) {
-          sr += red[buf][c][b][w].x;
-          si += red[buf][c][b][w].y;
-        }
-        const T cl = (T)Cn[l];
-        ALMT[alm_idx(l, m, L) * B + b0 + b] = cmk<C>(cl * sr, cl * si);
-      }
-    }
-    buf ^= 1;
   }
-  // coefficients below the first seed are exactly zero contributions
-  for (int l = m + tid; l < min(l_begin, L + 1); l += NT)
+  // partials red[w * H + h][l - l0][b]; the reads below walk l
+  __syncthreads();
+  {
+    const int u = slot / BG, b = slot % BG;
 #pragma unroll
-    for (int b = 0; b < BG; ++b)
-      if (b0 + b < B) ALMT[alm_idx(l, m, L) * B + b0 + b] = cmk<C>(0, 0);
+    for (int q = 0; q < NG; ++q) tile[((w * H + h) * kBlockL + q * SL + u) * BG + b] = acc[q];
+  }
+  __syncthreads();
+  const double *Cn = tb.coefC + aoff;
+  const size_t nalm = nalm_of(L);
+  const size_t base = alm_idx(l0, m, L);
+  const T f = (m == 0) ? f0 : fm;
+  for (int e = tid; e < BG * kBlockL; e += 256) {
+    const int b = e / kBlockL, lrel = e % kBlockL;
+    const int l = l0 + lrel;
+    if (l > L) continue;
+    T re = 0, im = 0;
+#pragma unroll
+    for (int pp = 0; pp < NW * H; ++pp) {
+      const C v = tile[(pp * kBlockL + lrel) * BG + b];
+      re += v.x;
+      im += v.y;
+    }
+    const T gsc = f * (T)Cn[l];
+    C val = cmk<C>(gsc * re, (m == 0) ? (T)0 : gsc * im);
+    C *dst = alm + (size_t)(b0 + b) * nalm + base + lrel;
+    if (accum) {
+      const C o = *dst;
+      val.x += o.x;
+      val.y += o.y;
+    }
+    *dst = val;
+  }
 }
 
 // Synthesis: one wave per workgroup = (m, 64 ring pairs), one ring pair per
@@ -257,28 +277,32 @@ __global__ void __launch_bounds__(64)
   }
 }
 
-template <typename T, int BG, int NT, int RPT>
-static void launch_fwd_cfg(const Tables &tb, int B, int b0, const cplx<T> *XE, const cplx<T> *XO, cplx<T> *ALMT,
-                           hipStream_t st) {
-  hipLaunchKernelGGL((k_legendre_fwd_valu<T, BG, NT, RPT>), dim3(tb.lmax + 1), dim3(NT), 0, st, tb, B, b0, XE, XO,
-                     ALMT);
+template <typename T, int BG, int R>
+static void launch_fwd_cfg(const Tables &tb, int B, int b0, const cplx<T> *XE, const cplx<T> *XO, cplx<T> *alm,
+                           double f0, double fm, int accum, hipStream_t st) {
+  int longest = 0;  // items of the largest XCD group (m = x mod 8, blocks of kBlockL l's)
+  for (int x = 0; x < 8; ++x) {
+    int c = 0;
+    for (int m = x; m <= tb.lmax; m += 8) c += (tb.lmax - m + kBlockL) / kBlockL;
+    longest = std::max(longest, c);
+  }
+  hipLaunchKernelGGL((k_legendre_fwd_valu<T, BG, R>), dim3(8 * longest), dim3(256), 0, st, tb, B, b0, XE, XO, alm,
+                     (T)f0, (T)fm, accum);
 }
 
+// Channel groups of 2 (FP64) or 4 (FP32), then 2 and 1 for the rest; writes
+// the caller's layout (factors f0 for m = 0 and fm for m > 0, optionally
+// added to what alm holds).
 template <typename T>
-hipError_t launch_legendre_fwd_valu(const Tables &tb, int B, const cplx<T> *XE, const cplx<T> *XO, cplx<T> *ALMT,
-                                    hipStream_t st) {
-  constexpr int BG = sizeof(T) == 8 ? 1 : 2;
-  const int Rp = tb.npairs;
-  for (int b0 = 0; b0 < B; b0 += BG) {
-    if (Rp <= 64)
-      launch_fwd_cfg<T, BG, 64, 1>(tb, B, b0, XE, XO, ALMT, st);
-    else if (Rp <= 1024)
-      launch_fwd_cfg<T, BG, 256, 4>(tb, B, b0, XE, XO, ALMT, st);
-    else if (Rp <= 2048)
-      launch_fwd_cfg<T, BG, 1024, 2>(tb, B, b0, XE, XO, ALMT, st);
-    else
-      launch_fwd_cfg<T, BG, 1024, 4>(tb, B, b0, XE, XO, ALMT, st);
+hipError_t launch_legendre_fwd_valu(const Tables &tb, int B, const cplx<T> *XE, const cplx<T> *XO, cplx<T> *alm,
+                                    double f0, double fm, int accum, hipStream_t st) {
+  if (tb.nitems == 0) return hipErrorInvalidValue;
+  int b0 = 0;
+  if constexpr (sizeof(T) == 4) {
+    for (; b0 + 4 <= B; b0 += 4) launch_fwd_cfg<T, 4, 2>(tb, B, b0, XE, XO, alm, f0, fm, accum, st);
   }
+  for (; b0 + 2 <= B; b0 += 2) launch_fwd_cfg<T, 2, 2>(tb, B, b0, XE, XO, alm, f0, fm, accum, st);
+  if (b0 < B) launch_fwd_cfg<T, 1, 4>(tb, B, b0, XE, XO, alm, f0, fm, accum, st);
   return hipGetLastError();
 }
 
@@ -308,9 +332,9 @@ hipError_t launch_legendre_inv_valu(const Tables &tb, int B, const cplx<T> *ALMT
 }
 
 template hipError_t launch_legendre_fwd_valu<double>(const Tables &, int, const double2 *, const double2 *, double2 *,
-                                                     hipStream_t);
+                                                     double, double, int, hipStream_t);
 template hipError_t launch_legendre_fwd_valu<float>(const Tables &, int, const float2 *, const float2 *, float2 *,
-                                                    hipStream_t);
+                                                    double, double, int, hipStream_t);
 template hipError_t launch_legendre_inv_valu<double>(const Tables &, int, const double2 *, SynLayout, double2 *,
                                                      double2 *, hipStream_t);
 template hipError_t launch_legendre_inv_valu<float>(const Tables &, int, const float2 *, SynLayout, float2 *,

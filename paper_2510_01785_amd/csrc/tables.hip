@@ -66,6 +66,10 @@ __global__ void k_ring_pairs(int N, int *rp_n, int *rp_sN, int *rp_sS, int *p0n,
 __global__ void k_coefs(int L, double *coefA, double *coefC) {
   const int m = blockIdx.x * blockDim.x + threadIdx.x;
   if (m > L) return;
+  if (m == L) {
+    const size_t n = nalm_of(L);
+    for (size_t i = 0; i < kCoefPadTable; ++i) coefA[n + i] = coefC[n + i] = 0.0;
+  }
   const double dm = m;
   double c2 = 1.0, c1 = 1.0;  // c_{l-2}, c_{l-1}
   size_t base = alm_idx(m, m, L);

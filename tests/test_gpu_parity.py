@@ -137,14 +137,25 @@ def test_bf16_input_map2alm(shtx):
     assert rel_l2(got.cpu().numpy(), ref) <= 1e-5
 
 
-@pytest.mark.parametrize("nside,lmax,batch,force_valu", [(32, 95, 16, "0"), (64, 255, 20, "0"), (32, 95, 7, "1"),
-                                                         (64, 191, 1, "1"), (16, 47, 3, "0")])
-def test_fp32_legendre_paths(shtx, nside, lmax, batch, force_valu, monkeypatch):
-    """FP32 through the matrix-core Legendre kernels (default) and through the
-    vector-ALU kernels (SHTX_FORCE_VALU=1, read by the library per call), each
-    against the oracle."""
-    monkeypatch.setenv("SHTX_FORCE_VALU", force_valu)
-    announce("fp32 legendre path valu=%s nside=%d lmax=%d B=%d" % (force_valu, nside, lmax, batch))
+# path: "mfma" forces the matrix-core Legendre kernels for every batch size,
+# "valu" the vector-ALU kernels, "default" leaves the library's choice (the
+# vector-ALU kernels below 5 channels).  Both switches are read per call.
+_PATH_ENV = {"mfma": ("0", "1"), "valu": ("1", "1"), "default": ("0", None)}
+
+
+@pytest.mark.parametrize("nside,lmax,batch,path", [(32, 95, 16, "mfma"), (64, 255, 20, "mfma"), (16, 47, 3, "mfma"),
+                                                   (32, 95, 7, "valu"), (64, 191, 1, "valu"), (32, 95, 6, "valu"),
+                                                   (64, 191, 3, "default"), (64, 191, 9, "default")])
+def test_fp32_legendre_paths(shtx, nside, lmax, batch, path, monkeypatch):
+    """FP32 through the matrix-core and the vector-ALU Legendre kernels,
+    each against the oracle."""
+    force, min_batch = _PATH_ENV[path]
+    monkeypatch.setenv("SHTX_FORCE_VALU", force)
+    if min_batch is None:
+        monkeypatch.delenv("SHTX_MFMA_MIN_BATCH", raising=False)
+    else:
+        monkeypatch.setenv("SHTX_MFMA_MIN_BATCH", min_batch)
+    announce("fp32 legendre path %s nside=%d lmax=%d B=%d" % (path, nside, lmax, batch))
     f = synth.white_map(99, batch, geometry.npix(nside))
     x = torch.tensor(f, dtype=torch.float32, device="cuda")
     ref = sht.map2alm(x.double().cpu().numpy(), lmax, nside)
