@@ -65,9 +65,12 @@ __host__ __device__ inline int largest_odd_prime(int i) {
 }
 
 // Bluestein convolution length for ring length 4i, or 0 for mixed radix.
+// Such a ring is transformed as four DFTs of length i (its samples 4j + q,
+// q = 0..3) combined by one radix-4 step; each length-i DFT is a cyclic
+// convolution of length M >= 2i - 1.
 __host__ __device__ inline int bluestein_len(int i) {
   if (largest_odd_prime(i) <= kMaxDirectPrime) return 0;
-  const int need = 2 * (4 * i) - 1;
+  const int need = 2 * i - 1;
   int M = 1;
   while (M < need) M <<= 1;
   return M;
@@ -88,9 +91,10 @@ inline void bluestein_sizes(int nside, size_t *total, int *mmax) {
 
 // Ring FFT launch geometry (ring_fft.hip): workgroup size NT, channels per
 // workgroup G (the channel slice of a ring pair), LDS bytes, offset of the
-// twiddle table in LDS and whether Bluestein rings are transformed as such.
+// twiddle table in LDS and how many of a Bluestein ring's four
+// sub-transforms share one FFT call (4 or 1).
 struct FftGeom {
-  int NT, G, tq_off, use_bs;
+  int NT, G, tq_off, bs_nb;
   size_t lds;
 };
 FftGeom fft_geometry(int nside, int mmax_bs, int batch, size_t csize);

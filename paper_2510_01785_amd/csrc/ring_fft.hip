@@ -20,7 +20,8 @@
 
 namespace shtx {
 
-constexpr int kFftOutMax = 16;  // complex values per thread per stage
+constexpr int kFftOutMax = 16;    // complex values per thread per stage
+constexpr int kFftThreads = 512;  // threads per workgroup
 
 // Index of logical element o in the LDS work buffer.  Transforms of length
 // >= 256 insert one padding slot every 16 elements, so that the stride-R
@@ -416,46 +417,133 @@ __device__ __forceinline__ void load_octant(cplx<T> *tq, const cplx<T> *__restri
   for (int r = threadIdx.x; r <= N / 8; r += NT) tq[r] = src[r * rs];
 }
 
-// LDS layout flag of a ring pass: the transform length is the ring length n,
-// or the Bluestein length M when M > 0.
-__device__ __forceinline__ int pass_pad(int n, int M) { return (M ? M : n) >= kPadMin; }
-
 // Forward DFT of gc channels of ring-pair p held in buf (channel-major, LDS
 // layout lidx(., pad)); tq is LDS space for an octant root table.  Every
-// thread of the workgroup calls this (it synchronises internally).
-//
-// Rings with a prime factor above kMaxDirectPrime (M > 0, one channel at a
-// time) take Bluestein's DFT (Eq. (17)-(23)): with the chirp
-// c_j = exp(-i pi j^2/n), X_k = c_k sum_j (x_j c_j) conj(c_{k-j}); the
-// convolution is done cyclically on the power-of-two length M >= 2n-1 with
-// the precomputed transform bhat of conj(c) and two power-of-two FFTs (the
-// inverse one through conjugation), the chirp products, the zero padding and
-// the product with bhat fused into their first and last stages.  One call
-// site of the power-of-two FFT serves both cases.
+// thread of the workgroup calls this (it synchronises internally).  Ring
+// lengths with a power-of-two part only take radix-16 Stockham stages, the
+// others (prime factors <= kMaxDirectPrime) mixed-radix stages.
 template <typename T, int NT>
-__device__ __forceinline__ void ring_dft(const Tables &tb, int p, int M, cplx<T> *buf, cplx<T> *tq, int n, int gc,
-                                         int pad, bool tq_ready) {
-  const bool p2 = (n & (n - 1)) == 0;
-  if (M == 0 && !p2) {
+__device__ __forceinline__ void ring_dft(const Tables &tb, cplx<T> *buf, cplx<T> *tq, int n, int gc, int pad,
+                                         bool tq_ready) {
+  if (n & (n - 1)) {
     fft_mixed<T, NT>(buf, n, gc, pad, TabOf<T>::roots(tb) + roots_offset(n >> 2));
     return;
   }
-  const int N = M ? M : n;
   if (!tq_ready) {
-    if (M) load_octant<T, NT>(tq, TabOf<T>::rootsP(tb), M, tb.mmax_bs / M);
-    else load_octant<T, NT>(tq, TabOf<T>::roots(tb) + roots_offset(n >> 2), n, 1);
+    load_octant<T, NT>(tq, TabOf<T>::roots(tb) + roots_offset(n >> 2), n, 1);
     __syncthreads();
   }
-  const size_t co = roots_offset(n >> 2);
-  const Fuse<T> fz{TabOf<T>::chirp(tb) + co, M ? TabOf<T>::bhat(tb) + tb.rp_bsoff[p] : nullptr, n,
-                   (T)1 / (T)N};
-  const int logN = __builtin_ctz(N);
-  const int npass = M ? 2 : 1;
-  for (int ps = 0; ps < npass; ++ps) {
-    const int fin = (M && ps == 0) ? kInChirp : kInPlain;
-    const int fout = M ? (ps == 0 ? kOutBhat : kOutChirp) : kOutPlain;
-    fft_p2<T, NT>(buf, logN, gc, pad, tq, fz, fin, fout);
+  const Fuse<T> fz{nullptr, nullptr, n, (T)1};
+  fft_p2<T, NT>(buf, __builtin_ctz(n), gc, pad, tq, fz, kInPlain, kOutPlain);
+}
+
+// A Bluestein ring's four length-i sub-transforms run as the channels of
+// power-of-two FFT calls, nb = 4, 2 or 1 per call (as many as one stage and
+// the LDS hold).  The results of the calls before the last wait in LDS; with
+// nb = 1, FP64 keeps the third in registers, which makes the LDS need fit at
+// nside 2048.
+template <typename T> struct BsLayout {
+  static constexpr int kLdsY1 = sizeof(T) == 8 ? 2 : 3;  // results kept in LDS when nb = 1
+};
+template <int NT> struct BsSlots {  // values of s < i per thread (i < kMaxNside)
+  static constexpr int value = (kMaxNside + NT - 1) / NT;
+};
+
+// Forward DFT of one channel of a ring of length n = 4i whose i has a prime
+// factor above kMaxDirectPrime (Bluestein ring, convolution length M):
+//   X[s + i r] = sum_q w_n^{q s} (-i)^{q r} Y_q[s],  s < i, r, q = 0..3,
+// with Y_q the length-i DFT of the samples x[4j + q].  Each Y_q is Bluestein's
+// DFT (Eq. (17)-(23)): with the chirp c_j = exp(-i pi j^2 / i),
+// Y_q[s] = c_s sum_j (x[4j + q] c_j) conj(c_{s-j}), the convolution done
+// cyclically on length M with the precomputed transform bhat of conj(c) and
+// two power-of-two FFTs (the inverse one through conjugation); the chirp
+// products, the zero padding and the product with bhat are fused into their
+// first and last stages.  input(k) returns x[k].  LDS: the results kept
+// there at [q i, (q+1) i), then nb convolution channels (layout lidx(., M >=
+// kPadMin) each).  X ends in buf[0, n) unpadded.  tq holds (or receives) the
+// octant table of M.
+template <typename T, int NT, typename In>
+__device__ __forceinline__ void ring_dft_bs4(const Tables &tb, int p, int M, int nb, cplx<T> *buf, cplx<T> *tq,
+                                             int n, bool tq_ready, In input) {
+  using C = cplx<T>;
+  constexpr int NS = BsSlots<NT>::value;
+  const int i = n >> 2;
+  const int padM = M >= kPadMin;
+  const int cs = lstride(M, padM);                                   // convolution channel stride
+  const int ylds = nb == 4 ? 0 : nb == 2 ? 2 : BsLayout<T>::kLdsY1;  // results kept in LDS
+  const int qlast = 4 - nb;                                          // first result of the last call
+  C *wb = buf + ylds * i;                                            // convolution buffer
+  if (!tq_ready) {
+    load_octant<T, NT>(tq, TabOf<T>::rootsP(tb), M, tb.mmax_bs / M);
+    __syncthreads();
   }
+  const Fuse<T> fz{TabOf<T>::chirp(tb) + roots_offset(i), TabOf<T>::bhat(tb) + tb.rp_bsoff[p], i, (T)1 / (T)M};
+  const int logM = __builtin_ctz(M);
+  // opaque copies of the thread index per phase (as in stage_p2): index
+  // arithmetic hoisted out of the pass loop would stay live and spill
+  int tid = threadIdx.x;
+  C yr[NS];  // a result kept in registers (nb = 1, FP64)
+#pragma unroll 1
+  for (int q0 = 0; q0 < 4; q0 += nb) {
+    tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    for (int e = tid; e < nb * i; e += NT) {
+      const int c = e / i, j = e - c * i;
+      wb[c * cs + lidx(j, padM)] = input(4 * j + q0 + c);
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int ps = 0; ps < 2; ++ps)
+      fft_p2<T, NT>(wb, logM, nb, padM, tq, fz, ps == 0 ? kInChirp : kInPlain, ps == 0 ? kOutBhat : kOutChirp);
+    if (q0 == qlast) break;  // the last results stay in the convolution buffer
+    tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+#pragma unroll
+    for (int u = 0; u < NS; ++u) {
+      const int s = tid + u * NT;
+      if (s < i) {
+        for (int c = 0; c < nb; ++c) {
+          const C v = wb[c * cs + lidx(s, padM)];
+          if (q0 + c < ylds || BsLayout<T>::kLdsY1 > 2) buf[(q0 + c) * i + s] = v;
+          else yr[u] = v;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // radix-4 combination: all four results of this thread's s into registers,
+  // then X over the same LDS
+  const C *w = TabOf<T>::roots(tb) + roots_offset(i);  // w_n^e, e < n
+  tid = threadIdx.x;
+  asm volatile("" : "+v"(tid));
+  C z[NS][4];
+#pragma unroll
+  for (int u = 0; u < NS; ++u) {
+    const int s = tid + u * NT;
+    if (s < i) {
+      C y[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        y[q] = q >= qlast                                  ? wb[(q - qlast) * cs + lidx(s, padM)]
+               : (q < ylds || BsLayout<T>::kLdsY1 > 2) ? buf[q * i + s]
+                                                         : yr[u];
+      z[u][0] = y[0];
+      z[u][1] = cmul(y[1], w[s]);
+      z[u][2] = cmul(y[2], w[2 * s]);
+      z[u][3] = cmul(y[3], w[3 * s]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < NS; ++u) {
+    const int s = tid + u * NT;
+    if (s < i) {
+      dft4(z[u][0], z[u][1], z[u][2], z[u][3]);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) buf[s + r * i] = z[u][r];
+    }
+  }
+  __syncthreads();
 }
 
 // Workgroup -> (ring pair, channel slice).  A ring pair's channels are split
@@ -514,8 +602,8 @@ __device__ __forceinline__ void store_pair(double2 *p, double2 a, double2 b) {
 constexpr int kLoadUnroll = 2;  // quads of pixels in flight per thread
 
 template <typename TIn, typename T, int NT>
-__global__ void __launch_bounds__(NT, (sizeof(T) == 4 && NT == 512) ? 4 : 1)
-    k_ring_fft_fwd(Tables tb, int B, int G, int use_bs, int tq_off, const TIn *__restrict__ map,
+__global__ void __launch_bounds__(NT, sizeof(T) == 4 ? 4 : 1)
+    k_ring_fft_fwd(Tables tb, int B, int G, int tq_off, int bs_nb, const TIn *__restrict__ map,
                    const double *__restrict__ wtab, double wscale, cplx<T> *__restrict__ XE,
                    cplx<T> *__restrict__ XO) {
   using C = cplx<T>;
@@ -531,44 +619,54 @@ __global__ void __launch_bounds__(NT, (sizeof(T) == 4 && NT == 512) ? 4 : 1)
   const T w = (T)(wtab ? wtab[p] * wscale : wscale);
   const int num = tb.rp_p0n[p], den = tb.rp_p0d[p];
   const size_t npix = (size_t)tb.npix;
-  const int Mbs = use_bs ? tb.rp_M[p] : 0;
-  const int pad = pass_pad(n, Mbs);
+  const int Mbs = tb.rp_M[p];
+  const int pad = Mbs == 0 && n >= kPadMin;  // Bluestein rings leave their DFT unpadded
   const int Gp = Mbs ? 1 : G;
   const int nq = n >> 2;  // quads of pixels per ring
   const int tid = threadIdx.x;
 #pragma unroll 1
   for (int b0 = bg0; b0 < bg1; b0 += Gp) {
     const int gc = min(Gp, bg1 - b0);
-    // rings -> LDS, packed as (f_N + f_S) + i (f_N - f_S); every load of the
-    // pass is issued before the LDS writes
+    if (Mbs) {
+      // Bluestein ring: samples read per sub-transform, packed on the fly
+      const TIn *row = map + (size_t)b0 * npix;
+      auto input = [&](int k) {
+        const T a = load_as<T, TIn>(row + sN + k), b = equator ? (T)0 : load_as<T, TIn>(row + sS + k);
+        return cmk<C>(a + b, a - b);
+      };
+      ring_dft_bs4<T, NT>(tb, p, Mbs, bs_nb, buf, tq, n, b0 != bg0, input);
+    } else {
+      // rings -> LDS, packed as (f_N + f_S) + i (f_N - f_S); every load of the
+      // pass is issued before the LDS writes
 #pragma unroll 1
-    for (int q0 = tid; q0 < gc * nq; q0 += kLoadUnroll * NT) {
-      T fN[kLoadUnroll][4], fS[kLoadUnroll][4];
+      for (int q0 = tid; q0 < gc * nq; q0 += kLoadUnroll * NT) {
+        T fN[kLoadUnroll][4], fS[kLoadUnroll][4];
 #pragma unroll
-      for (int u = 0; u < kLoadUnroll; ++u) {
-        const int q = q0 + u * NT;
-        if (q < gc * nq) {
-          const int c = q / nq, j = 4 * (q - c * nq);
-          const TIn *row = map + (size_t)(b0 + c) * npix + j;
-          load4<T, TIn>(row + sN, fN[u]);
-          if (!equator) load4<T, TIn>(row + sS, fS[u]);
+        for (int u = 0; u < kLoadUnroll; ++u) {
+          const int q = q0 + u * NT;
+          if (q < gc * nq) {
+            const int c = q / nq, j = 4 * (q - c * nq);
+            const TIn *row = map + (size_t)(b0 + c) * npix + j;
+            load4<T, TIn>(row + sN, fN[u]);
+            if (!equator) load4<T, TIn>(row + sS, fS[u]);
+          }
         }
-      }
 #pragma unroll
-      for (int u = 0; u < kLoadUnroll; ++u) {
-        const int q = q0 + u * NT;
-        if (q < gc * nq) {
-          const int c = q / nq, j = 4 * (q - c * nq);
+        for (int u = 0; u < kLoadUnroll; ++u) {
+          const int q = q0 + u * NT;
+          if (q < gc * nq) {
+            const int c = q / nq, j = 4 * (q - c * nq);
 #pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const T a = fN[u][e], b = equator ? (T)0 : fS[u][e];
-            buf[lidx(c * n + j + e, pad)] = cmk<C>(a + b, a - b);
+            for (int e = 0; e < 4; ++e) {
+              const T a = fN[u][e], b = equator ? (T)0 : fS[u][e];
+              buf[lidx(c * n + j + e, pad)] = cmk<C>(a + b, a - b);
+            }
           }
         }
       }
+      __syncthreads();
+      ring_dft<T, NT>(tb, buf, tq, n, gc, pad, b0 != bg0);
     }
-    __syncthreads();
-    ring_dft<T, NT>(tb, p, Mbs, buf, tq, n, gc, pad, b0 != bg0);
     // E/O spectra for m = 0..L; one phase per m, channels contiguous
     const size_t obase = (size_t)p * M * B + b0;
     const bool pairs = ((B | b0) & 1) == 0;  // channel pairs start 16-byte aligned
@@ -612,8 +710,8 @@ __global__ void __launch_bounds__(NT, (sizeof(T) == 4 && NT == 512) ? 4 : 1)
 constexpr int kFoldUnroll = 2;  // (k, channel) items per thread with loads in flight
 
 template <typename TOut, typename T, int NT>
-__global__ void __launch_bounds__(NT, (sizeof(T) == 4 && NT == 512) ? 4 : 1)
-    k_ring_fft_inv(Tables tb, int B, int G, int use_bs, int tq_off, const cplx<T> *__restrict__ GN,
+__global__ void __launch_bounds__(NT, sizeof(T) == 4 ? 4 : 1)
+    k_ring_fft_inv(Tables tb, int B, int G, int tq_off, int bs_nb, const cplx<T> *__restrict__ GN,
                    const cplx<T> *__restrict__ GS, const TOut *__restrict__ sub, TOut *__restrict__ map) {
   using C = cplx<T>;
   extern __shared__ unsigned char smem_raw[];
@@ -627,10 +725,10 @@ __global__ void __launch_bounds__(NT, (sizeof(T) == 4 && NT == 512) ? 4 : 1)
   const int L = tb.lmax, M = L + 1;
   const int num = tb.rp_p0n[p], den = tb.rp_p0d[p];
   const size_t npix = (size_t)tb.npix;
-  const int Mbs = use_bs ? tb.rp_M[p] : 0;
-  const int pad = pass_pad(n, Mbs);
+  const int Mbs = tb.rp_M[p];
+  const int pad = Mbs == 0 && n >= kPadMin;  // Bluestein rings leave their DFT unpadded
   const int Gp = Mbs ? 1 : G;
-  const int tid = threadIdx.x;
+  int tid = threadIdx.x;
   // c_m = g_m exp(+i m phi0)
   auto phased = [&](const C *src, int m) {
     const int red = (int)(((long long)m * num) % (2 * den));
@@ -639,70 +737,90 @@ __global__ void __launch_bounds__(NT, (sizeof(T) == 4 && NT == 512) ? 4 : 1)
   // this workgroup's channel slice [m][G] of the synthesis spectra
   const int ns = (B + G - 1) / G;
   const size_t sbase = ((size_t)p * ns + bg0 / G) * M * G;
+  // Fold onto k = m mod n (positive frequencies) and k = -m mod n (negative,
+  // conj) for channel c of the slice at gn / gs: the first term of each sum is
+  // loaded by fold_load (so that several items can have their loads in
+  // flight), fold_value adds the phases and further aliases (short rings) and
+  // returns conj(h), h = C_N + i C_S, so that a forward DFT gives conj(IDFT(h)).
+  auto fold_load = [&](const C *gn, const C *gs, int k, int c, C &pn, C &ps, C &qn, C &qs) {
+    const int m1 = k, m2 = (k == 0) ? n : n - k;
+    pn = ps = qn = qs = cmk<C>(0, 0);
+    if (m1 < M) {
+      pn = gn[(size_t)m1 * G + c];
+      if (!equator) ps = gs[(size_t)m1 * G + c];
+    }
+    if (m2 < M) {
+      qn = gn[(size_t)m2 * G + c];
+      if (!equator) qs = gs[(size_t)m2 * G + c];
+    }
+  };
+  auto fold_value = [&](const C *gn, const C *gs, int k, int c, C pn, C ps, C qn, C qs) {
+    C cn = cmk<C>(0, 0), cs = cmk<C>(0, 0);
+    const int m1 = k, m2 = (k == 0) ? n : n - k;
+    if (m1 < M) {
+      const int red = (int)(((long long)m1 * num) % (2 * den));
+      const C ph = phase_pi<T>(red, den, (T)1);
+      cn = cmul(pn, ph);
+      cs = cmul(ps, ph);
+      if (m1 == 0) {
+        cn.y = 0;
+        cs.y = 0;
+      }
+    }
+    if (m2 < M) {
+      const int red = (int)(((long long)m2 * num) % (2 * den));
+      const C ph = phase_pi<T>(red, den, (T)1);
+      cn = cadd(cn, cconj(cmul(qn, ph)));
+      cs = cadd(cs, cconj(cmul(qs, ph)));
+    }
+    for (int m = m1 + n; m < M; m += n) {
+      cn = cadd(cn, phased(gn + c, m));
+      if (!equator) cs = cadd(cs, phased(gs + c, m));
+    }
+    for (int m = m2 + n; m < M; m += n) {
+      cn = cadd(cn, cconj(phased(gn + c, m)));
+      if (!equator) cs = cadd(cs, cconj(phased(gs + c, m)));
+    }
+    return cmk<C>(cn.x - cs.y, -(cn.y + cs.x));
+  };
 #pragma unroll 1
   for (int b0 = bg0; b0 < bg1; b0 += Gp) {
+    // opaque thread index per channel pass: keeps the pass's index and
+    // address arithmetic inside the loop (hoisted, it would spill)
+    tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
     const int gc = min(Gp, bg1 - b0);
     const C *gn = GN + sbase + (b0 - bg0);
     const C *gs = GS + sbase + (b0 - bg0);
-    // fold onto k = m mod n (positive frequencies) and k = -m mod n (negative,
-    // conj); the first term of each sum is loaded for kFoldUnroll items at
-    // once, further aliases (short rings) in a loop
+    if (Mbs) {
+      // Bluestein ring: folded values computed per sub-transform sample
+      auto input = [&](int k) {
+        C pn, ps, qn, qs;
+        fold_load(gn, gs, k, 0, pn, ps, qn, qs);
+        return fold_value(gn, gs, k, 0, pn, ps, qn, qs);
+      };
+      ring_dft_bs4<T, NT>(tb, p, Mbs, bs_nb, buf, tq, n, b0 != bg0, input);
+    } else {
 #pragma unroll 1
-    for (int j0 = tid; j0 < gc * n; j0 += kFoldUnroll * NT) {
-      C pn[kFoldUnroll], ps[kFoldUnroll], qn[kFoldUnroll], qs[kFoldUnroll];
+      for (int j0 = tid; j0 < gc * n; j0 += kFoldUnroll * NT) {
+        C pn[kFoldUnroll], ps[kFoldUnroll], qn[kFoldUnroll], qs[kFoldUnroll];
 #pragma unroll
-      for (int u = 0; u < kFoldUnroll; ++u) {
-        const int j = j0 + u * NT;
-        const int k = j / gc, c = j - k * gc;  // channel fastest: adjacent channels adjacent in memory
-        const int m1 = k, m2 = (k == 0) ? n : n - k;
-        const bool ok = j < gc * n;
-        pn[u] = ps[u] = qn[u] = qs[u] = cmk<C>(0, 0);
-        if (ok && m1 < M) {
-          pn[u] = gn[(size_t)m1 * G + c];
-          if (!equator) ps[u] = gs[(size_t)m1 * G + c];
+        for (int u = 0; u < kFoldUnroll; ++u) {
+          const int j = j0 + u * NT;
+          const int k = j / gc, c = j - k * gc;  // channel fastest: adjacent channels adjacent in memory
+          if (j < gc * n) fold_load(gn, gs, k, c, pn[u], ps[u], qn[u], qs[u]);
         }
-        if (ok && m2 < M) {
-          qn[u] = gn[(size_t)m2 * G + c];
-          if (!equator) qs[u] = gs[(size_t)m2 * G + c];
+#pragma unroll
+        for (int u = 0; u < kFoldUnroll; ++u) {
+          const int j = j0 + u * NT;
+          if (j >= gc * n) continue;
+          const int k = j / gc, c = j - k * gc;
+          buf[lidx(c * n + k, pad)] = fold_value(gn, gs, k, c, pn[u], ps[u], qn[u], qs[u]);
         }
       }
-#pragma unroll
-      for (int u = 0; u < kFoldUnroll; ++u) {
-        const int j = j0 + u * NT;
-        if (j >= gc * n) continue;
-        const int k = j / gc, c = j - k * gc;
-        C cn = cmk<C>(0, 0), cs = cmk<C>(0, 0);
-        const int m1 = k, m2 = (k == 0) ? n : n - k;
-        if (m1 < M) {
-          const int red = (int)(((long long)m1 * num) % (2 * den));
-          const C ph = phase_pi<T>(red, den, (T)1);
-          cn = cmul(pn[u], ph);
-          cs = cmul(ps[u], ph);
-          if (m1 == 0) {
-            cn.y = 0;
-            cs.y = 0;
-          }
-        }
-        if (m2 < M) {
-          const int red = (int)(((long long)m2 * num) % (2 * den));
-          const C ph = phase_pi<T>(red, den, (T)1);
-          cn = cadd(cn, cconj(cmul(qn[u], ph)));
-          cs = cadd(cs, cconj(cmul(qs[u], ph)));
-        }
-        for (int m = m1 + n; m < M; m += n) {
-          cn = cadd(cn, phased(gn + c, m));
-          if (!equator) cs = cadd(cs, phased(gs + c, m));
-        }
-        for (int m = m2 + n; m < M; m += n) {
-          cn = cadd(cn, cconj(phased(gn + c, m)));
-          if (!equator) cs = cadd(cs, cconj(phased(gs + c, m)));
-        }
-        // h = C_N + i C_S ; store conj(h) so that a forward DFT gives conj(IDFT(h))
-        buf[lidx(c * n + k, pad)] = cmk<C>(cn.x - cs.y, -(cn.y + cs.x));
-      }
+      __syncthreads();
+      ring_dft<T, NT>(tb, buf, tq, n, gc, pad, b0 != bg0);
     }
-    __syncthreads();
-    ring_dft<T, NT>(tb, p, Mbs, buf, tq, n, gc, pad, b0 != bg0);
     if (sub) {
       // residual sub - S a of an iterative refinement (TOut = T)
       for (int j = tid; j < gc * n; j += NT) {
@@ -725,19 +843,15 @@ __global__ void __launch_bounds__(NT, (sizeof(T) == 4 && NT == 512) ? 4 : 1)
   }
 }
 
-// Launch geometry: threads per workgroup, channels per workgroup and LDS
-// bytes.  One stage holds NT * kFftOutMax complex values in registers, so
-// NT = 512 covers ring and Bluestein lengths up to 8192 without spilling; the
-// 16384-point Bluestein transforms of FP32 at nside 2048 take NT = 1024.
-// Bluestein rings need M complex values of LDS; where that does not fit
-// (FP64 at nside 2048) every ring takes the mixed-radix path (use_bs = 0).
+// Launch geometry: channels per workgroup and LDS bytes.  One stage holds
+// kFftThreads * kFftOutMax complex values in registers, which covers ring
+// lengths up to 4 * 2048; Bluestein rings use convolution lengths M < 2 nside.
 constexpr size_t kMaxLds = 160 * 1024;  // LDS of one gfx950 workgroup
 
 FftGeom fft_geometry(int nside, int mmax_bs, int batch, size_t csize) {
   FftGeom g{};
   const int nmax = 4 * nside;
-  const int need_pts = nmax > mmax_bs ? nmax : mmax_bs;
-  g.NT = (csize == 8 && need_pts > 512 * kFftOutMax) ? 1024 : 512;
+  g.NT = kFftThreads;
   const int cap = g.NT * kFftOutMax;  // complex values one stage can hold
   int G = cap / nmax;
   const int lds_cap = (int)((72 * 1024) / (nmax * csize));
@@ -746,13 +860,27 @@ FftGeom fft_geometry(int nside, int mmax_bs, int batch, size_t csize) {
   if (G > 16) G = 16;
   if (G < 1) G = 1;
   g.G = G;
-  size_t need = (size_t)G * nmax;
-  g.use_bs = mmax_bs > 0 && mmax_bs <= cap && (lds_elems(mmax_bs) + mmax_bs / 8 + 1) * csize <= kMaxLds;
-  if (g.use_bs && (size_t)mmax_bs > need) need = mmax_bs;
+  size_t need = lds_elems((size_t)G * nmax);
   // octant root table of the largest power-of-two length used
-  const int npow = g.use_bs && mmax_bs > nmax ? mmax_bs : nmax;
-  g.tq_off = (int)lds_elems(need);
-  g.lds = (lds_elems(need) + npow / 8 + 1) * csize;
+  const int npow = mmax_bs > nmax ? mmax_bs : nmax;
+  const size_t tqn = npow / 8 + 1;
+  g.bs_nb = 4;
+  if (mmax_bs > 0) {
+    // Bluestein rings (i < nside): the most sub-transforms per FFT call that
+    // one stage (cap values) and the LDS hold
+    const size_t cs = mmax_bs + (mmax_bs >= kPadMin ? mmax_bs / 16 : 0);
+    const size_t ylds1 = csize == 16 ? BsLayout<double>::kLdsY1 : BsLayout<float>::kLdsY1;
+    size_t bs = 0;
+    for (int nb = 4; nb >= 1; nb >>= 1) {
+      const size_t ylds = nb == 4 ? 0 : nb == 2 ? 2 : ylds1;
+      bs = ylds * (size_t)(nside - 1) + nb * cs;
+      g.bs_nb = nb;
+      if ((size_t)nb * mmax_bs <= (size_t)cap && ((bs > need ? bs : need) + tqn) * csize <= kMaxLds) break;
+    }
+    if (bs > need) need = bs;
+  }
+  g.tq_off = (int)need;
+  g.lds = (need + tqn) * csize;
   return g;
 }
 
@@ -770,19 +898,12 @@ template <typename TIn, typename T>
 hipError_t launch_ring_fft_fwd(Tables tb, int B, const TIn *map, const double *wtab, double wscale, cplx<T> *XE,
                                cplx<T> *XO, hipStream_t st) {
   const FftGeom g = fft_geometry(tb.nside, tb.mmax_bs, B, sizeof(cplx<T>));
-  const dim3 grid(fft_grid(tb.npairs, B, g.G));
-  if (sizeof(T) == 8 || g.NT == 512) {  // FP64 geometry always takes 512 threads
-    auto kern = k_ring_fft_fwd<TIn, T, 512>;
-    hipError_t e = allow_lds(kern, g.lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, grid, dim3(512), g.lds, st, tb, B, g.G, g.use_bs, g.tq_off, map, wtab, wscale, XE, XO);
-  } else if constexpr (sizeof(T) == 4) {
-    auto kern = k_ring_fft_fwd<TIn, T, 1024>;
-    hipError_t e = allow_lds(kern, g.lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, grid, dim3(1024), g.lds, st, tb, B, g.G, g.use_bs, g.tq_off, map, wtab, wscale, XE,
-                       XO);
-  }
+  if (g.lds > kMaxLds) return hipErrorInvalidValue;
+  auto kern = k_ring_fft_fwd<TIn, T, kFftThreads>;
+  hipError_t e = allow_lds(kern, g.lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kern, dim3(fft_grid(tb.npairs, B, g.G)), dim3(kFftThreads), g.lds, st, tb, B, g.G, g.tq_off,
+                     g.bs_nb, map, wtab, wscale, XE, XO);
   return hipGetLastError();
 }
 
@@ -790,18 +911,12 @@ template <typename TOut, typename T>
 hipError_t launch_ring_fft_inv(Tables tb, int B, const cplx<T> *GN, const cplx<T> *GS, const TOut *sub, TOut *map,
                                hipStream_t st) {
   const FftGeom g = fft_geometry(tb.nside, tb.mmax_bs, B, sizeof(cplx<T>));
-  const dim3 grid(fft_grid(tb.npairs, B, g.G));
-  if (sizeof(T) == 8 || g.NT == 512) {  // FP64 geometry always takes 512 threads
-    auto kern = k_ring_fft_inv<TOut, T, 512>;
-    hipError_t e = allow_lds(kern, g.lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, grid, dim3(512), g.lds, st, tb, B, g.G, g.use_bs, g.tq_off, GN, GS, sub, map);
-  } else if constexpr (sizeof(T) == 4) {
-    auto kern = k_ring_fft_inv<TOut, T, 1024>;
-    hipError_t e = allow_lds(kern, g.lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, grid, dim3(1024), g.lds, st, tb, B, g.G, g.use_bs, g.tq_off, GN, GS, sub, map);
-  }
+  if (g.lds > kMaxLds) return hipErrorInvalidValue;
+  auto kern = k_ring_fft_inv<TOut, T, kFftThreads>;
+  hipError_t e = allow_lds(kern, g.lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kern, dim3(fft_grid(tb.npairs, B, g.G)), dim3(kFftThreads), g.lds, st, tb, B, g.G, g.tq_off,
+                     g.bs_nb, GN, GS, sub, map);
   return hipGetLastError();
 }
 

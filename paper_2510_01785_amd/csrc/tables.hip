@@ -183,34 +183,33 @@ __global__ void k_roots(int N, double2 *r64, float2 *r32) {
   r32[o] = make_float2((float)c, (float)-s);
 }
 
-// Bluestein chirp c_j = exp(-i pi j^2 / n) for j < n = 4i (Eq. (19)), with
-// j^2 reduced modulo 2n exactly.
+// Bluestein chirp c_j = exp(-i pi j^2 / i) for j < i (Eq. (19) for the
+// length-i DFTs of a ring of length 4i), with j^2 reduced modulo 2i exactly;
+// stored at the ring's offset in the root-table layout.
 __global__ void k_chirp(int N, double2 *c64, float2 *c32) {
   const int i = blockIdx.y + 1;
   if (bluestein_len(i) == 0) return;
-  const int n = 4 * i;
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= n) return;
-  const int r = (int)(((long long)j * j) % (2 * n));
+  if (j >= i) return;
+  const int r = (int)(((long long)j * j) % (2 * i));
   double s, c;
-  sincospi((double)r / (double)n, &s, &c);
+  sincospi((double)r / (double)i, &s, &c);
   const size_t o = roots_offset(i) + j;
   c64[o] = make_double2(c, -s);
   c32[o] = make_float2((float)c, (float)-s);
 }
 
-// b_j = conj(c_{|j|}) for |j| < n, wrapped onto length M, zero elsewhere.
+// b_j = conj(c_{|j|}) for |j| < i, wrapped onto length M, zero elsewhere.
 __global__ void k_bhat_init(int N, const int *rp_bsoff, const double2 *c64, double2 *buf) {
   const int i = blockIdx.y + 1;
   const int M = bluestein_len(i);
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (M == 0 || j >= M) return;
-  const int n = 4 * i;
   const double2 *c = c64 + roots_offset(i);
   double2 v = make_double2(0.0, 0.0);
-  if (j < n)
+  if (j < i)
     v = make_double2(c[j].x, -c[j].y);
-  else if (j > M - n)
+  else if (j > M - i)
     v = make_double2(c[M - j].x, -c[M - j].y);
   buf[rp_bsoff[i - 1] + j] = v;
 }
@@ -342,7 +341,7 @@ hipError_t launch_tables_build(int nside, int lmax, void *base, hipStream_t st) 
     auto D2 = [&](size_t off) { return reinterpret_cast<double2 *>(b + off); };
     auto F2 = [&](size_t off) { return reinterpret_cast<float2 *>(b + off); };
     const int ncap = nside - 1;
-    hipLaunchKernelGGL(k_chirp, dim3((4 * nside + 255) / 256, ncap), dim3(256), 0, st, nside, D2(o.chirp64),
+    hipLaunchKernelGGL(k_chirp, dim3((nside + 255) / 256, ncap), dim3(256), 0, st, nside, D2(o.chirp64),
                        F2(o.chirp32));
     hipLaunchKernelGGL(k_bhat_init, dim3((o.mmax_bs + 255) / 256, ncap), dim3(256), 0, st, nside, I(o.rp_bsoff),
                        D2(o.chirp64), D2(o.bhat_tmp));
