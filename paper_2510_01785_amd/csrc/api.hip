@@ -29,7 +29,7 @@ hipError_t launch_legendre_fwd_mfma(const Tables &, int, const float2 *, const f
                                     hipStream_t);
 hipError_t launch_legendre_inv_mfma(const Tables &, int, const float2 *, SynLayout, float2 *, float2 *, hipStream_t);
 template <typename T, typename TI>
-hipError_t launch_alm_in(int, int, const cplx<TI> *, const double *, cplx<T> *, double, double, double,
+hipError_t launch_alm_in(int, int, int, const cplx<TI> *, const double *, cplx<T> *, double, double, double,
                          hipStream_t);
 
 namespace {
@@ -176,13 +176,19 @@ template <> hipError_t legendre_fwd<float>(const Tables &tb, int B, const float2
     return launch_legendre_fwd_mfma(tb, B, XE, XO, alm, f0, fm, accum, st);
   return launch_legendre_fwd_valu<float>(tb, B, XE, XO, alm, f0, fm, accum, st);
 }
+// Synthesis Legendre kernel of a call: matrix cores (FP32, enough channels)
+// or vector ALUs; the choice also fixes the channel groups of the
+// coefficient buffer (chan_group): one group of all channels for the matrix
+// cores, the vector-ALU kernels' groups otherwise.
+template <typename T> bool inv_on_mfma(int B) { return sizeof(T) == 4 && B >= mfma_min_batch() && !force_valu(); }
+
 template <typename T> hipError_t legendre_inv(const Tables &tb, int B, const cplx<T> *ALMT, SynLayout lay,
-                                              cplx<T> *GN, cplx<T> *GS, hipStream_t st) {
+                                              cplx<T> *GN, cplx<T> *GS, bool mfma, hipStream_t st) {
   return launch_legendre_inv_valu<T>(tb, B, ALMT, lay, GN, GS, st);
 }
 template <> hipError_t legendre_inv<float>(const Tables &tb, int B, const float2 *ALMT, SynLayout lay, float2 *GN,
-                                           float2 *GS, hipStream_t st) {
-  if (B >= mfma_min_batch() && !force_valu()) return launch_legendre_inv_mfma(tb, B, ALMT, lay, GN, GS, st);
+                                           float2 *GS, bool mfma, hipStream_t st) {
+  if (mfma) return launch_legendre_inv_mfma(tb, B, ALMT, lay, GN, GS, st);
   return launch_legendre_inv_valu<float>(tb, B, ALMT, lay, GN, GS, st);
 }
 
@@ -206,16 +212,18 @@ template <typename TOut, typename T>
 int run_synthesis(const Tables &tb, int B, const cplx<T> *alm, TOut *map, double s, double f0, double fm, void *work,
                   hipStream_t st, const TOut *sub = nullptr) {
   Work<T> w = carve<T>(work, tb, B);
+  const bool mfma = inv_on_mfma<T>(B);  // read once: both kernels follow the same choice
   hipError_t e;
   {
     StageTimer t(kStAlmIn, st);
-    e = launch_alm_in<T, T>(tb.lmax, B, alm, tb.coefC, w.almt, s, f0, fm, st);
+    const int gmax = mfma ? B : sizeof(T) == 8 ? 2 : 4;
+    e = launch_alm_in<T, T>(tb.lmax, B, gmax, alm, tb.coefC, w.almt, s, f0, fm, st);
   }
   if (e != hipSuccess) return SHTX_ERR_HIP;
   {
     StageTimer t(kStLegInv, st);
     e = legendre_inv<T>(tb, B, w.almt, syn_layout(tb.nside, tb.lmax, tb.mmax_bs, B, sizeof(cplx<T>)), w.specA,
-                        w.specB, st);
+                        w.specB, mfma, st);
   }
   if (e != hipSuccess) return SHTX_ERR_HIP;
   StageTimer t(kStFftInv, st);

@@ -119,10 +119,28 @@ inline SynLayout syn_layout(int nside, int lmax, int mmax_bs, int batch, size_t 
 // groups of 8 coefficients without clamping at lmax; the values loaded past
 // lmax only meet masked terms).
 constexpr size_t kCoefPad = 8;
+// Channel groups of the synthesis coefficient buffer ALMT (written by the
+// input layout kernel, read by the synthesis Legendre kernels): channels
+// [g0, g0 + w) are stored as [idx][w] from complex offset g0 (nalm +
+// kCoefPad).  gmax = batch gives one group, the plain [idx][batch] layout of
+// the matrix-core kernel; gmax = 4 or 2 (vector-ALU kernels) gives full groups
+// of gmax, then one of 2 (if two or three channels remain with gmax = 4) and
+// one of 1, the channel groups those kernels are launched on.
+struct ChanGroup {
+  int g0, w;
+};
+__host__ __device__ inline ChanGroup chan_group(int b, int batch, int gmax) {
+  const int nfull = batch / gmax * gmax;
+  if (b < nfull) return ChanGroup{b / gmax * gmax, gmax};
+  if (batch - nfull >= 2 && b < nfull + 2) return ChanGroup{nfull, 2};
+  return ChanGroup{batch - 1, 1};
+}
+
 // Zero doubles after the last recurrence coefficient in the table buffer: the
-// analysis kernels load the coefficients of a whole 128-l block without
-// clamping at lmax (rows past lmax are never stored).
-constexpr size_t kCoefPadTable = kBlockL;
+// analysis kernels load the coefficients of a whole 128-l block, and the 8
+// after it ahead of time, without clamping at lmax (rows past lmax are never
+// stored).
+constexpr size_t kCoefPadTable = kBlockL + 8;
 
 // Byte offsets of the pieces of the resident table buffer.
 struct TableOffsets {

@@ -1,6 +1,7 @@
 // Conversion of the caller's coefficient layout alm[b][idx(l,m)] into the
-// transposed internal layout ALMT[idx(l,m)][b] of the synthesis Legendre
-// kernels, with the per-coefficient scale factors of each entry point:
+// transposed internal layout of the synthesis Legendre kernels, ALMT[idx][b]
+// per channel group (chan_group), with the per-coefficient scale factors of
+// each entry point:
 //
 //   ALMT = s * f_m * c_lm * alm   (Im of m = 0 ignored)
 //
@@ -14,12 +15,12 @@ namespace shtx {
 // A workgroup takes kLayoutThreads consecutive coefficient indices idx(l, m)
 // (m = 0 exactly for idx <= lmax) and 16 channels at a time, through an LDS
 // tile: the caller side alm[b][idx] is read along idx and the internal side
-// ALMT[idx][b] written as one contiguous run, both coalesced.
+// written as contiguous runs of each channel group, both coalesced.
 constexpr int kLayoutThreads = 256;
 
 template <typename T, typename TI>
 __global__ void __launch_bounds__(kLayoutThreads)
-    k_alm_in(int L, int B, const cplx<TI> *__restrict__ alm, const double *__restrict__ coefC,
+    k_alm_in(int L, int B, int gmax, const cplx<TI> *__restrict__ alm, const double *__restrict__ coefC,
              cplx<T> *__restrict__ ALMT, double s, double f0, double fm) {
   using C = cplx<T>;
   __shared__ C tile[kLayoutThreads][17];
@@ -44,23 +45,25 @@ __global__ void __launch_bounds__(kLayoutThreads)
     __syncthreads();
     for (int q = t; q < ni * nb; q += kLayoutThreads) {
       const int r = q / nb, b = q - r * nb;
-      ALMT[(i0 + r) * B + b0 + b] = tile[r][b];
+      const ChanGroup gr = chan_group(b0 + b, B, gmax);
+      ALMT[(size_t)gr.g0 * (nalm + kCoefPad) + (i0 + r) * gr.w + (b0 + b - gr.g0)] = tile[r][b];
     }
     __syncthreads();
   }
 }
 
 template <typename T, typename TI>
-hipError_t launch_alm_in(int L, int B, const cplx<TI> *alm, const double *coefC, cplx<T> *ALMT, double s,
-                         double f0, double fm, hipStream_t st) {
+hipError_t launch_alm_in(int L, int B, int gmax, const cplx<TI> *alm, const double *coefC, cplx<T> *ALMT,
+                         double s, double f0, double fm, hipStream_t st) {
   const dim3 grid((unsigned)((nalm_of(L) + kLayoutThreads - 1) / kLayoutThreads));
-  hipLaunchKernelGGL((k_alm_in<T, TI>), grid, dim3(kLayoutThreads), 0, st, L, B, alm, coefC, ALMT, s, f0, fm);
+  hipLaunchKernelGGL((k_alm_in<T, TI>), grid, dim3(kLayoutThreads), 0, st, L, B, gmax, alm, coefC, ALMT, s, f0,
+                     fm);
   return hipGetLastError();
 }
 
-template hipError_t launch_alm_in<double, double>(int, int, const double2 *, const double *, double2 *, double,
-                                                  double, double, hipStream_t);
-template hipError_t launch_alm_in<float, float>(int, int, const float2 *, const double *, float2 *, double, double,
-                                                double, hipStream_t);
+template hipError_t launch_alm_in<double, double>(int, int, int, const double2 *, const double *, double2 *,
+                                                  double, double, double, hipStream_t);
+template hipError_t launch_alm_in<float, float>(int, int, int, const float2 *, const double *, float2 *, double,
+                                                double, double, hipStream_t);
 
 }  // namespace shtx

@@ -97,7 +97,17 @@ __global__ void __launch_bounds__(256)
         xo[r][b] = XO[o + b];
       }
     }
-    double a8[8];
+    // recurrence coefficients, 8 per scalar load, one group of 8 steps ahead;
+    // the opaque offsets keep the compiler from hoisting the loads of later
+    // groups (SGPR pressure).  Past lmax the table's zero padding is read
+    // (rows that are never stored).
+    double a8[8], a8n[8];
+    {
+      int ao = aoff + l0 + g_begin * SL;
+      asm volatile("" : "+s"(ao));
+#pragma unroll
+      for (int i = 0; i < 8; ++i) a8n[i] = ((const cdouble *)tb.coefA)[ao + i];
+    }
 #pragma unroll
     for (int q = 0; q < NG; ++q) {
       if (q < g_begin || q >= ng_end) continue;  // uniform
@@ -105,13 +115,13 @@ __global__ void __launch_bounds__(256)
       for (int u = 0; u < SL; ++u) {
         const int t = q * SL + u;
         if (u % 8 == 0) {
-          // 8 coefficients per scalar load; the opaque offset keeps the loads
-          // of later groups from being hoisted (SGPR pressure).  Past lmax
-          // the table's zero padding is read (rows that are never stored).
-          int ao = aoff + l0 + t;
+          int ao = aoff + l0 + t + 8;
           asm volatile("" : "+s"(ao));
 #pragma unroll
-          for (int i = 0; i < 8; ++i) a8[i] = ((const cdouble *)tb.coefA)[ao + i];
+          for (int i = 0; i < 8; ++i) {
+            a8[i] = a8n[i];
+            a8n[i] = ((const cdouble *)tb.coefA)[ao + i];
+          }
         }
         const double a = a8[u % 8];
 #pragma unroll
@@ -192,6 +202,15 @@ __global__ void __launch_bounds__(256)
   }
 }
 
+// v where keep, else +0 (bit mask: a NaN in unused padding is dropped too,
+// and the load stays unconditional).
+__device__ __forceinline__ double keep_if(double v, bool keep) {
+  return __longlong_as_double(__double_as_longlong(v) & (keep ? -1LL : 0LL));
+}
+__device__ __forceinline__ float keep_if(float v, bool keep) {
+  return __uint_as_float(__float_as_uint(v) & (keep ? 0xffffffffu : 0u));
+}
+
 // Synthesis: one wave per workgroup = (m, 64 ring pairs), one ring pair per
 // lane; every lane runs its ring's recurrence and accumulates S_e and S_o
 // for BG channels itself (no reduction).  The lanes step through l together
@@ -227,19 +246,53 @@ __global__ void __launch_bounds__(64)
   const int wl = __builtin_amdgcn_readfirstlane(wlv);
   const int aoff = m * (2 * L + 1 - m) / 2;  // alm_idx(m, m, L) - m
   const cdouble *A = (const cdouble *)tb.coefA + aoff;
-  // a[l][b] (re, im) of this channel group: T index (aoff + l) * 2B + 2(b0 + b) + {0, 1}
-  const creal *a = (const creal *)ALMT + (size_t)aoff * 2 * B + 2 * b0;
-  const int arow = 2 * B;
+  // a[l][b] (re, im) of this channel group, stored [idx][BG] (chan_group):
+  // T index 2 ((aoff + l) BG + b) + {0, 1} from the group's base
+  const size_t nalm = nalm_of(L);
+  const creal *a = (const creal *)ALMT + 2 * ((size_t)b0 * (nalm + kCoefPad) + (size_t)aoff * BG);
   T se[BG][2], so[BG][2];
 #pragma unroll
   for (int b = 0; b < BG; ++b) se[b][0] = se[b][1] = so[b][0] = so[b][1] = (T)0;
   double prv = 0.0, cur = 0.0;
 #pragma unroll 1
   for (int lq = wl; lq <= L; lq += 8) {
-    T lam[8];
+    // all scalar loads of the group first, one wait: 8 recurrence
+    // coefficients and 8 contiguous rows of a (the buffer has padding rows
+    // past lmax; in the last group their values are replaced by zeros)
+    double Ag[8];
+    T ar[8][BG], ai[8][BG];
+    const creal *g = a + (size_t)lq * (2 * BG);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) Ag[u] = A[lq + u];  // coefficients padded past lmax
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+#pragma unroll
+      for (int b = 0; b < BG; ++b) {
+        ar[u][b] = g[2 * (u * BG + b)];
+        ai[u][b] = g[2 * (u * BG + b) + 1];
+      }
+    // all of them in SGPRs here: the loads are issued together and waited for
+    // once (left to itself the scheduler loads one row per step, each with
+    // its own wait)
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      const double nx = fma(A[lq + u] * z, cur, -prv);  // coefficients padded past lmax (unused values)
+      asm volatile("" : "+s"(Ag[u]));
+#pragma unroll
+      for (int b = 0; b < BG; ++b) asm volatile("" : "+s"(ar[u][b]), "+s"(ai[u][b]));
+    }
+    if (lq + 7 > L) {  // uniform: the last group
+#pragma unroll
+      for (int u = 1; u < 8; ++u)
+#pragma unroll
+        for (int b = 0; b < BG; ++b) {
+          const bool in = lq + u <= L;
+          ar[u][b] = keep_if(ar[u][b], in);
+          ai[u][b] = keep_if(ai[u][b], in);
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const double nx = fma(Ag[u] * z, cur, -prv);
       if (u == 0) {
         const bool inj = (lq == ls);
         prv = inj ? sd.x : cur;
@@ -248,21 +301,15 @@ __global__ void __launch_bounds__(64)
         prv = cur;
         cur = nx;
       }
-      lam[u] = (T)cur;
-    }
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      if (lq + u > L) break;  // last group: rows past lmax (padding) are not read
-      const creal *row = a + (size_t)(lq + u) * arow;
+      const T lam = (T)cur;
 #pragma unroll
       for (int b = 0; b < BG; ++b) {
-        const T ar = row[2 * b], ai = row[2 * b + 1];
         if (u & 1) {
-          so[b][0] = fma(lam[u], ar, so[b][0]);
-          so[b][1] = fma(lam[u], ai, so[b][1]);
+          so[b][0] = fma(lam, ar[u][b], so[b][0]);
+          so[b][1] = fma(lam, ai[u][b], so[b][1]);
         } else {
-          se[b][0] = fma(lam[u], ar, se[b][0]);
-          se[b][1] = fma(lam[u], ai, se[b][1]);
+          se[b][0] = fma(lam, ar[u][b], se[b][0]);
+          se[b][1] = fma(lam, ai[u][b], se[b][1]);
         }
       }
     }
