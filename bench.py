@@ -56,16 +56,21 @@ def parse():
 
 
 # Legendre kernels: the library takes the matrix-core kernels for FP32 /
-# BF16 contraction from this many channels up (its default switch point),
+# BF16 contraction from this many channels up (its default switch points),
 # the vector-ALU kernels otherwise
-MFMA_MIN_BATCH = 5
+MFMA_MIN_BATCH = {"fwd": 5, "inv": 8}
 
 
-def stage_kernel(stage, mfma):
+def on_mfma(stage, dtype, batch):
+    d = stage.split("_")[1]
+    return dtype in ("f32", "bf16") and batch >= MFMA_MIN_BATCH[d]
+
+
+def stage_kernel(stage, dtype, batch):
     """(kernel symbol, source file) that runs `stage`."""
     if stage.startswith("legendre"):
         d = stage.split("_")[1]
-        return ("k_legendre_%s_mfma" % d, "legendre_mfma.hip") if mfma else \
+        return ("k_legendre_%s_mfma" % d, "legendre_mfma.hip") if on_mfma(stage, dtype, batch) else \
             ("k_legendre_%s_valu" % d, "legendre_valu.hip")
     return {"ring_fft_fwd": ("k_ring_fft_fwd", "ring_fft.hip"),
             "ring_fft_inv": ("k_ring_fft_inv", "ring_fft.hip"),
@@ -341,7 +346,7 @@ def main():
     npix = 12 * nside * nside
     spec_bytes = 2 * (lmax + 1) * 2 * nside * B * csize
     alm_bytes = (lmax + 1) * (lmax + 2) // 2 * B * csize
-    mfma = args.dtype in ("f32", "bf16") and B >= MFMA_MIN_BATCH
+    mfma = dom.startswith("legendre") and on_mfma(dom, args.dtype, B)
     leg_bound = "mfma" if mfma else "alu"
     # Legendre work: 4 flops (complex += real * complex) per executed (l, m,
     # ring pair) triple and channel; the executed triangle skips the l where
@@ -366,7 +371,7 @@ def main():
         achieved = amount / sec / 1e9
         peak = PEAK["hbm_GBs"]
     workload = "nside%d_lmax%d_b%d_%s" % (nside, lmax, B, args.dtype)
-    kname, kfile = stage_kernel(dom, mfma)
+    kname, kfile = stage_kernel(dom, args.dtype, B)
     traffic = measured_traffic(kname, kfile, workload) if (mfma or unit != "TFLOP/s") else None
     roof = dict(kernel=kname, bound=bound, achieved=round(achieved, 3), peak=peak, unit=unit,
                 frac=round(achieved / peak, 4), traffic=traffic,

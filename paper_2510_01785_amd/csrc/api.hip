@@ -151,13 +151,14 @@ constexpr int kMaxIter = 64;  // refinement iterations accepted by shtx_map2alm_
 int status_of(hipError_t e) { return e == hipSuccess ? SHTX_OK : SHTX_ERR_HIP; }
 
 // Matrix-core Legendre kernels serve FP32 contraction from mfma_min_batch()
-// channels up (SHTX_MFMA_MIN_BATCH, default 5: below that the 32-column
-// matrix tiles are mostly padding and the vector-ALU kernels are faster);
-// SHTX_FORCE_VALU=1 in the environment selects the vector-ALU kernels
-// everywhere.  Both are read per call.
-int mfma_min_batch() {
+// channels up: 5 for the analysis, 8 for the synthesis by default (below
+// that the 32-column matrix tiles are mostly padding and the vector-ALU
+// kernels are faster); SHTX_MFMA_MIN_BATCH sets both.  SHTX_FORCE_VALU=1 in
+// the environment selects the vector-ALU kernels everywhere.  Both are read
+// per call.
+int mfma_min_batch(bool synthesis) {
   const char *e = getenv("SHTX_MFMA_MIN_BATCH");
-  return e ? atoi(e) : 5;
+  return e ? atoi(e) : synthesis ? 8 : 5;
 }
 bool force_valu() {
   const char *e = getenv("SHTX_FORCE_VALU");
@@ -172,7 +173,7 @@ template <typename T> hipError_t legendre_fwd(const Tables &tb, int B, const cpl
 }
 template <> hipError_t legendre_fwd<float>(const Tables &tb, int B, const float2 *XE, const float2 *XO, float2 *alm,
                                            double f0, double fm, int accum, hipStream_t st) {
-  if (B >= mfma_min_batch() && mfma_fwd_supported(tb) && !force_valu())
+  if (B >= mfma_min_batch(false) && mfma_fwd_supported(tb) && !force_valu())
     return launch_legendre_fwd_mfma(tb, B, XE, XO, alm, f0, fm, accum, st);
   return launch_legendre_fwd_valu<float>(tb, B, XE, XO, alm, f0, fm, accum, st);
 }
@@ -180,7 +181,9 @@ template <> hipError_t legendre_fwd<float>(const Tables &tb, int B, const float2
 // or vector ALUs; the choice also fixes the channel groups of the
 // coefficient buffer (chan_group): one group of all channels for the matrix
 // cores, the vector-ALU kernels' groups otherwise.
-template <typename T> bool inv_on_mfma(int B) { return sizeof(T) == 4 && B >= mfma_min_batch() && !force_valu(); }
+template <typename T> bool inv_on_mfma(int B) {
+  return sizeof(T) == 4 && B >= mfma_min_batch(true) && !force_valu();
+}
 
 template <typename T> hipError_t legendre_inv(const Tables &tb, int B, const cplx<T> *ALMT, SynLayout lay,
                                               cplx<T> *GN, cplx<T> *GS, bool mfma, hipStream_t st) {

@@ -211,16 +211,17 @@ __device__ __forceinline__ float keep_if(float v, bool keep) {
   return __uint_as_float(__float_as_uint(v) & (keep ? 0xffffffffu : 0u));
 }
 
-// Synthesis: one wave per workgroup = (m, 64 ring pairs), one ring pair per
-// lane; every lane runs its ring's recurrence and accumulates S_e and S_o
-// for BG channels itself (no reduction).  The lanes step through l together
-// from the wave's earliest seed, 8 steps per group: seeds sit at l = m + 8j,
-// so within a group l - m is even exactly at the even steps.  The recurrence
-// coefficients and the coefficients a_l of the BG channels are wave-uniform
-// and come through scalar loads (32-bit offsets into the constant address
-// space).  Workgroups are dealt so that the 64-ring chunks of one m run on
-// one XCD.
-template <typename T, int BG>
+// Synthesis: one wave per workgroup = (m, 64 R ring pairs), R ring pairs
+// per lane (p = chunk 64 R + 64 r + lane); every lane runs its rings'
+// recurrences and accumulates S_e and S_o for BG channels itself (no
+// reduction).  The lanes step through l together from the wave's earliest
+// seed, 8 steps per group: seeds sit at l = m + 8j, so within a group l - m is
+// even exactly at the even steps.  The recurrence coefficients and the
+// coefficients a_l of the BG channels are wave-uniform: one batch of scalar
+// loads per group (32-bit offsets into the constant address space) serves
+// all R rings.  Workgroups are dealt so that the chunks of one m run on one
+// XCD.
+template <typename T, int BG, int R>
 __global__ void __launch_bounds__(64)
     k_legendre_inv_valu(Tables tb, int B, int b0, const cplx<T> *__restrict__ ALMT, SynLayout lay,
                         cplx<T> *__restrict__ GN, cplx<T> *__restrict__ GS) {
@@ -228,19 +229,27 @@ __global__ void __launch_bounds__(64)
   typedef __attribute__((address_space(4))) const double cdouble;
   typedef __attribute__((address_space(4))) const T creal;
   const int L = tb.lmax, Rp = tb.npairs;
-  const int nch = (Rp + 63) / 64;
+  const int nch = (Rp + 64 * R - 1) / (64 * R);
   const int g = blockIdx.x;
   const int x = g & 7, q = g >> 3;
   const int m = x + 8 * (q / nch);
   const int chunk = q % nch;
   if (m > L) return;  // uniform
   const int j = threadIdx.x;
-  const int p = chunk * 64 + j;
-  const bool valid = p < Rp;
-  const double z = valid ? tb.rp_z[p] : 0.0;
-  const int ls = valid ? tb.seed_l[(size_t)m * Rp + p] : L + 1;
-  const double2 sd = valid ? tb.seed_v[(size_t)m * Rp + p] : make_double2(0.0, 0.0);
-  int wlv = ls;
+  double z[R], prv[R], cur[R];
+  double2 sd[R];
+  int ls[R];
+  int wlv = L + 1;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int p = chunk * 64 * R + 64 * r + j;
+    const bool valid = p < Rp;
+    z[r] = valid ? tb.rp_z[p] : 0.0;
+    ls[r] = valid ? tb.seed_l[(size_t)m * Rp + p] : L + 1;
+    sd[r] = valid ? tb.seed_v[(size_t)m * Rp + p] : make_double2(0.0, 0.0);
+    prv[r] = cur[r] = 0.0;
+    wlv = min(wlv, ls[r]);
+  }
 #pragma unroll
   for (int o = 1; o < 64; o <<= 1) wlv = min(wlv, __shfl_xor(wlv, o));
   const int wl = __builtin_amdgcn_readfirstlane(wlv);
@@ -250,10 +259,11 @@ __global__ void __launch_bounds__(64)
   // T index 2 ((aoff + l) BG + b) + {0, 1} from the group's base
   const size_t nalm = nalm_of(L);
   const creal *a = (const creal *)ALMT + 2 * ((size_t)b0 * (nalm + kCoefPad) + (size_t)aoff * BG);
-  T se[BG][2], so[BG][2];
+  T se[R][BG][2], so[R][BG][2];
 #pragma unroll
-  for (int b = 0; b < BG; ++b) se[b][0] = se[b][1] = so[b][0] = so[b][1] = (T)0;
-  double prv = 0.0, cur = 0.0;
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int b = 0; b < BG; ++b) se[r][b][0] = se[r][b][1] = so[r][b][0] = so[r][b][1] = (T)0;
 #pragma unroll 1
   for (int lq = wl; lq <= L; lq += 8) {
     // all scalar loads of the group first, one wait: 8 recurrence
@@ -261,15 +271,15 @@ __global__ void __launch_bounds__(64)
     // past lmax; in the last group their values are replaced by zeros)
     double Ag[8];
     T ar[8][BG], ai[8][BG];
-    const creal *g = a + (size_t)lq * (2 * BG);
+    const creal *gp = a + (size_t)lq * (2 * BG);
 #pragma unroll
     for (int u = 0; u < 8; ++u) Ag[u] = A[lq + u];  // coefficients padded past lmax
 #pragma unroll
     for (int u = 0; u < 8; ++u)
 #pragma unroll
       for (int b = 0; b < BG; ++b) {
-        ar[u][b] = g[2 * (u * BG + b)];
-        ai[u][b] = g[2 * (u * BG + b) + 1];
+        ar[u][b] = gp[2 * (u * BG + b)];
+        ai[u][b] = gp[2 * (u * BG + b) + 1];
       }
     // all of them in SGPRs here: the loads are issued together and waited for
     // once (left to itself the scheduler loads one row per step, each with
@@ -292,35 +302,42 @@ __global__ void __launch_bounds__(64)
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      const double nx = fma(Ag[u] * z, cur, -prv);
-      if (u == 0) {
-        const bool inj = (lq == ls);
-        prv = inj ? sd.x : cur;
-        cur = inj ? sd.y : nx;
-      } else {
-        prv = cur;
-        cur = nx;
-      }
-      const T lam = (T)cur;
 #pragma unroll
-      for (int b = 0; b < BG; ++b) {
-        if (u & 1) {
-          so[b][0] = fma(lam, ar[u][b], so[b][0]);
-          so[b][1] = fma(lam, ai[u][b], so[b][1]);
+      for (int r = 0; r < R; ++r) {
+        const double nx = fma(Ag[u] * z[r], cur[r], -prv[r]);
+        if (u == 0) {
+          const bool inj = (lq == ls[r]);
+          prv[r] = inj ? sd[r].x : cur[r];
+          cur[r] = inj ? sd[r].y : nx;
         } else {
-          se[b][0] = fma(lam, ar[u][b], se[b][0]);
-          se[b][1] = fma(lam, ai[u][b], se[b][1]);
+          prv[r] = cur[r];
+          cur[r] = nx;
+        }
+        const T lam = (T)cur[r];
+#pragma unroll
+        for (int b = 0; b < BG; ++b) {
+          if (u & 1) {
+            so[r][b][0] = fma(lam, ar[u][b], so[r][b][0]);
+            so[r][b][1] = fma(lam, ai[u][b], so[r][b][1]);
+          } else {
+            se[r][b][0] = fma(lam, ar[u][b], se[r][b][0]);
+            se[r][b][1] = fma(lam, ai[u][b], se[r][b][1]);
+          }
         }
       }
     }
   }
-  if (!valid) return;
 #pragma unroll
-  for (int b = 0; b < BG; ++b) {
-    if (b0 + b >= B) continue;
-    const size_t o = lay.idx(p, b0 + b, m);
-    GN[o] = cmk<C>(se[b][0] + so[b][0], se[b][1] + so[b][1]);
-    GS[o] = cmk<C>(se[b][0] - so[b][0], se[b][1] - so[b][1]);
+  for (int r = 0; r < R; ++r) {
+    const int p = chunk * 64 * R + 64 * r + j;
+    if (p >= Rp) continue;
+#pragma unroll
+    for (int b = 0; b < BG; ++b) {
+      if (b0 + b >= B) continue;
+      const size_t o = lay.idx(p, b0 + b, m);
+      GN[o] = cmk<C>(se[r][b][0] + so[r][b][0], se[r][b][1] + so[r][b][1]);
+      GS[o] = cmk<C>(se[r][b][0] - so[r][b][0], se[r][b][1] - so[r][b][1]);
+    }
   }
 }
 
@@ -356,10 +373,11 @@ hipError_t launch_legendre_fwd_valu(const Tables &tb, int B, const cplx<T> *XE, 
 template <typename T, int BG>
 static void launch_inv_cfg(const Tables &tb, int B, int b0, const cplx<T> *ALMT, SynLayout lay, cplx<T> *GN,
                            cplx<T> *GS, hipStream_t st) {
-  const int nch = (tb.npairs + 63) / 64;
+  constexpr int R = BG == 1 ? 4 : 2;  // ring pairs per lane
+  const int nch = (tb.npairs + 64 * R - 1) / (64 * R);
   const int nm = (tb.lmax + 1 + 7) / 8;
-  hipLaunchKernelGGL((k_legendre_inv_valu<T, BG>), dim3(8 * nm * nch), dim3(64), 0, st, tb, B, b0, ALMT, lay, GN,
-                     GS);
+  hipLaunchKernelGGL((k_legendre_inv_valu<T, BG, R>), dim3(8 * nm * nch), dim3(64), 0, st, tb, B, b0, ALMT, lay,
+                     GN, GS);
 }
 
 // Channel groups of 4 (FP32) or 2 (FP64), then 2 and 1 for the rest: the

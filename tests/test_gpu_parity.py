@@ -139,13 +139,15 @@ def test_bf16_input_map2alm(shtx):
 
 # path: "mfma" forces the matrix-core Legendre kernels for every batch size,
 # "valu" the vector-ALU kernels, "default" leaves the library's choice (the
-# vector-ALU kernels below 5 channels).  Both switches are read per call.
+# vector-ALU kernels below 5 channels for the analysis, below 8 for the
+# synthesis).  Both switches are read per call.
 _PATH_ENV = {"mfma": ("0", "1"), "valu": ("1", "1"), "default": ("0", None)}
 
 
 @pytest.mark.parametrize("nside,lmax,batch,path", [(32, 95, 16, "mfma"), (64, 255, 20, "mfma"), (16, 47, 3, "mfma"),
                                                    (32, 95, 7, "valu"), (64, 191, 1, "valu"), (32, 95, 6, "valu"),
-                                                   (64, 191, 3, "default"), (64, 191, 9, "default")])
+                                                   (64, 191, 3, "default"), (64, 191, 6, "default"),
+                                                   (64, 191, 9, "default")])
 def test_fp32_legendre_paths(shtx, nside, lmax, batch, path, monkeypatch):
     """FP32 through the matrix-core and the vector-ALU Legendre kernels,
     each against the oracle."""
