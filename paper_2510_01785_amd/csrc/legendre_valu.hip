@@ -32,12 +32,13 @@ template <typename T> struct FwdValuShape {
   static constexpr int kRS = 65;                           // tile row stride in complex elements
 };
 
+// The LDS tile allows two workgroups (8 waves) per CU: the compiler may use
+// the registers of two waves per SIMD (loads kept in flight).
 template <typename T, int BG, int R>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
     k_legendre_fwd_valu(Tables tb, int B, int b0, const cplx<T> *__restrict__ XE, const cplx<T> *__restrict__ XO,
                         cplx<T> *__restrict__ alm, T f0, T fm, int accum) {
   using C = cplx<T>;
-  typedef __attribute__((address_space(4))) const double cdouble;
   constexpr int NW = 4;
   constexpr int SLOTS = FwdValuShape<T>::kSlots, RS = FwdValuShape<T>::kRS;
   constexpr int SL = SLOTS / BG;     // steps per transpose
@@ -47,6 +48,7 @@ __global__ void __launch_bounds__(256)
   static_assert(SL % 2 == 0 && kBlockL % SL == 0, "steps per transpose");
   static_assert(NW * H * kBlockL * BG <= NW * SLOTS * RS, "final reduction fits the tile");
   __shared__ C tile[NW * SLOTS * RS];
+  __shared__ double sA[kBlockL];  // the block's recurrence coefficients
 
   const int g = blockIdx.x;
   const int x = g & 7, k = g >> 3;
@@ -61,12 +63,25 @@ __global__ void __launch_bounds__(256)
   const int aoff = m * (2 * L + 1 - m) / 2;  // alm_idx(m, m, L) - m
   const int ng_end = min(NG, (L - l0) / SL + 1);  // transposes that hold a row l <= lmax
   C *tw = tile + w * SLOTS * RS;
+  // one coalesced read of the block's coefficients (past lmax: the table's
+  // zero padding, rows that are never stored)
+  if (tid < kBlockL) sA[tid] = tb.coefA[aoff + l0 + tid];
+  // Ring slices of 64 R rings go to the waves round-robin from the first
+  // active one: rings start earlier toward the equator, so the active slices
+  // of a block are (up to the discrete seeds) a suffix, and starting there
+  // balances them over the waves.  s0 counts the slices whose last ring is
+  // idle; every slice is still visited exactly once.
+  const int nsl = (Rp + 64 * R - 1) / (64 * R);
+  bool idle = false;
+  if (tid < nsl) idle = tb.ck_t[(size_t)item * Rp + min((tid + 1) * 64 * R, Rp) - 1] >= kBlockL;
+  const int s0 = __syncthreads_count(idle);
 
   C acc[NG];
 #pragma unroll
   for (int q = 0; q < NG; ++q) acc[q] = cmk<C>(0, 0);
 
-  for (int c0 = w * 64 * R; c0 < Rp; c0 += NW * 64 * R) {
+  for (int ks = w; ks < nsl; ks += NW) {
+    const int c0 = ((s0 + ks) % nsl) * 64 * R;
     int t0[R];
     int tmin = kBlockL;
 #pragma unroll
@@ -97,17 +112,7 @@ __global__ void __launch_bounds__(256)
         xo[r][b] = XO[o + b];
       }
     }
-    // recurrence coefficients, 8 per scalar load, one group of 8 steps ahead;
-    // the opaque offsets keep the compiler from hoisting the loads of later
-    // groups (SGPR pressure).  Past lmax the table's zero padding is read
-    // (rows that are never stored).
-    double a8[8], a8n[8];
-    {
-      int ao = aoff + l0 + g_begin * SL;
-      asm volatile("" : "+s"(ao));
-#pragma unroll
-      for (int i = 0; i < 8; ++i) a8n[i] = ((const cdouble *)tb.coefA)[ao + i];
-    }
+    double a8[8];
 #pragma unroll
     for (int q = 0; q < NG; ++q) {
       if (q < g_begin || q >= ng_end) continue;  // uniform
@@ -115,13 +120,8 @@ __global__ void __launch_bounds__(256)
       for (int u = 0; u < SL; ++u) {
         const int t = q * SL + u;
         if (u % 8 == 0) {
-          int ao = aoff + l0 + t + 8;
-          asm volatile("" : "+s"(ao));
 #pragma unroll
-          for (int i = 0; i < 8; ++i) {
-            a8[i] = a8n[i];
-            a8n[i] = ((const cdouble *)tb.coefA)[ao + i];
-          }
+          for (int i = 0; i < 8; ++i) a8[i] = sA[t + i];  // same address in every lane
         }
         const double a = a8[u % 8];
 #pragma unroll
@@ -152,16 +152,20 @@ __global__ void __launch_bounds__(256)
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      // all LPH reads in flight at once, then a pairwise sum (short chains)
       const C *src = tw + slot * RS + h * LPH;
-      T sr = 0, si = 0;
+      C e[LPH];
 #pragma unroll
-      for (int i = 0; i < LPH; ++i) {
-        const C e = src[i];
-        sr += e.x;
-        si += e.y;
-      }
-      acc[q].x += sr;
-      acc[q].y += si;
+      for (int i = 0; i < LPH; ++i) e[i] = src[i];
+#pragma unroll
+      for (int st = 1; st < LPH; st <<= 1)
+#pragma unroll
+        for (int i = 0; i < LPH; i += 2 * st) {
+          e[i].x += e[i + st].x;
+          e[i].y += e[i + st].y;
+        }
+      acc[q].x += e[0].x;
+      acc[q].y += e[0].y;
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
