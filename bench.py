@@ -381,7 +381,9 @@ def main():
         roof["triples_full"] = full
         roof["achieved_full_triangle"] = round(4.0 * full * B / sec / 1e12, 3)
     out = {
-        "metric": "SHT fwd+inv maps/s at Nside=1024 lmax=2047 B=16; % roofline; p50/p99 latency",
+        "metric": ("SHT fwd+inv maps/s at Nside=%d lmax=%d B=%d; %% roofline; p50/p99 latency" % (nside, lmax, B)
+                   if args.dtype != "bf16" else
+                   "SHT fwd maps/s at Nside=%d lmax=%d B=%d, BF16 maps; %% roofline; p50/p99 latency" % (nside, lmax, B)),
         "value": round(value, 3),
         "unit": "maps/s",
         "n_gpus": 1,
