@@ -458,13 +458,14 @@ template <int NT> struct BsSlots {  // values of s < i per thread (i < kMaxNside
 // cyclically on length M with the precomputed transform bhat of conj(c) and
 // two power-of-two FFTs (the inverse one through conjugation); the chirp
 // products, the zero padding and the product with bhat are fused into their
-// first and last stages.  input(k) returns x[k].  LDS: the results kept
-// there at [q i, (q+1) i), then nb convolution channels (layout lidx(., M >=
-// kPadMin) each).  X ends in buf[0, n) unpadded.  tq holds (or receives) the
+// first and last stages.  input(c, k) returns x[k] of channel c < gc (gc > 1
+// only with nb = 4).  LDS: the results kept there at [q i, (q+1) i), then the
+// gc nb convolution channels (layout lidx(., M >= kPadMin) each).  X of
+// channel c ends in buf[c n, (c+1) n) unpadded.  tq holds (or receives) the
 // octant table of M.
 template <typename T, int NT, typename In>
-__device__ __forceinline__ void ring_dft_bs4(const Tables &tb, int p, int M, int nb, cplx<T> *buf, cplx<T> *tq,
-                                             int n, bool tq_ready, In input) {
+__device__ __forceinline__ void ring_dft_bs4(const Tables &tb, int p, int M, int nb, int gc, cplx<T> *buf,
+                                             cplx<T> *tq, int n, bool tq_ready, In input) {
   using C = cplx<T>;
   constexpr int NS = BsSlots<NT>::value;
   const int i = n >> 2;
@@ -487,26 +488,28 @@ __device__ __forceinline__ void ring_dft_bs4(const Tables &tb, int p, int M, int
   for (int q0 = 0; q0 < 4; q0 += nb) {
     tid = threadIdx.x;
     asm volatile("" : "+v"(tid));
-    for (int e = tid; e < nb * i; e += NT) {
-      const int c = e / i, j = e - c * i;
-      wb[c * cs + lidx(j, padM)] = input(4 * j + q0 + c);
+    for (int e = tid; e < gc * nb * i; e += NT) {
+      const int cc = e / i, j = e - cc * i;  // convolution channel cc = (channel, sub-transform)
+      wb[cc * cs + lidx(j, padM)] = input(cc / nb, 4 * j + q0 + cc % nb);
     }
     __syncthreads();
 #pragma unroll 1
     for (int ps = 0; ps < 2; ++ps)
-      fft_p2<T, NT>(wb, logM, nb, padM, tq, fz, ps == 0 ? kInChirp : kInPlain, ps == 0 ? kOutBhat : kOutChirp);
+      fft_p2<T, NT>(wb, logM, gc * nb, padM, tq, fz, ps == 0 ? kInChirp : kInPlain,
+                    ps == 0 ? kOutBhat : kOutChirp);
     if (q0 == qlast) break;  // the last results stay in the convolution buffer
     tid = threadIdx.x;
     asm volatile("" : "+v"(tid));
+    if (BsLayout<T>::kLdsY1 < 3 && q0 >= ylds) {  // nb = 1: the result kept in registers
 #pragma unroll
-    for (int u = 0; u < NS; ++u) {
-      const int s = tid + u * NT;
-      if (s < i) {
-        for (int c = 0; c < nb; ++c) {
-          const C v = wb[c * cs + lidx(s, padM)];
-          if (q0 + c < ylds || BsLayout<T>::kLdsY1 > 2) buf[(q0 + c) * i + s] = v;
-          else yr[u] = v;
-        }
+      for (int u = 0; u < NS; ++u) {
+        const int s = tid + u * NT;
+        if (s < i) yr[u] = wb[lidx(s, padM)];
+      }
+    } else {
+      for (int e = tid; e < nb * i; e += NT) {
+        const int c = e / i, s = e - c * i;
+        buf[(q0 + c) * i + s] = wb[c * cs + lidx(s, padM)];
       }
     }
     __syncthreads();
@@ -519,14 +522,17 @@ __device__ __forceinline__ void ring_dft_bs4(const Tables &tb, int p, int M, int
   C z[NS][4];
 #pragma unroll
   for (int u = 0; u < NS; ++u) {
-    const int s = tid + u * NT;
-    if (s < i) {
+    const int e = tid + u * NT;  // (channel, s)
+    const int c = e / i, s = e - c * i;
+    if (c < gc) {
       C y[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
-        y[q] = q >= qlast                                  ? wb[(q - qlast) * cs + lidx(s, padM)]
-               : (q < ylds || BsLayout<T>::kLdsY1 > 2) ? buf[q * i + s]
-                                                         : yr[u];
+      for (int q = 0; q < 4; ++q) y[q] = q >= qlast ? wb[(c * nb + q - qlast) * cs + lidx(s, padM)] : buf[q * i + s];
+      if (BsLayout<T>::kLdsY1 < 3) {  // Y_2 from registers (a value select: yr stays in registers)
+        const bool reg = qlast > 2 && ylds <= 2;
+        y[2].x = reg ? yr[u].x : y[2].x;
+        y[2].y = reg ? yr[u].y : y[2].y;
+      }
       z[u][0] = y[0];
       z[u][1] = cmul(y[1], w[s]);
       z[u][2] = cmul(y[2], w[2 * s]);
@@ -536,14 +542,28 @@ __device__ __forceinline__ void ring_dft_bs4(const Tables &tb, int p, int M, int
   __syncthreads();
 #pragma unroll
   for (int u = 0; u < NS; ++u) {
-    const int s = tid + u * NT;
-    if (s < i) {
+    const int e = tid + u * NT;
+    const int c = e / i, s = e - c * i;
+    if (c < gc) {
       dft4(z[u][0], z[u][1], z[u][2], z[u][3]);
 #pragma unroll
-      for (int r = 0; r < 4; ++r) buf[s + r * i] = z[u][r];
+      for (int r = 0; r < 4; ++r) buf[c * n + s + r * i] = z[u][r];
     }
   }
   __syncthreads();
+}
+
+// Channels of a Bluestein ring per call of ring_dft_bs4: several when all
+// four sub-transforms share one call (nb = 4) and the stage (kFftOutMax per
+// thread), the LDS buffer (buf_elems) and the result slots hold them.
+template <int NT>
+__device__ __forceinline__ int bs_channels(int G, int nb, int M, int n, int buf_elems) {
+  if (nb != 4) return 1;
+  const int cs = lstride(M, M >= kPadMin);
+  int g = min(G, NT * kFftOutMax / (4 * M));
+  g = min(g, buf_elems / (4 * cs));
+  g = min(g, NT * BsSlots<NT>::value / (n >> 2));
+  return max(g, 1);
 }
 
 // Workgroup -> (ring pair, channel slice).  A ring pair's channels are split
@@ -621,7 +641,7 @@ __global__ void __launch_bounds__(NT, sizeof(T) == 4 ? 4 : 1)
   const size_t npix = (size_t)tb.npix;
   const int Mbs = tb.rp_M[p];
   const int pad = Mbs == 0 && n >= kPadMin;  // Bluestein rings leave their DFT unpadded
-  const int Gp = Mbs ? 1 : G;
+  const int Gp = Mbs ? bs_channels<NT>(G, bs_nb, Mbs, n, tq_off) : G;
   const int nq = n >> 2;  // quads of pixels per ring
   const int tid = threadIdx.x;
 #pragma unroll 1
@@ -629,12 +649,12 @@ __global__ void __launch_bounds__(NT, sizeof(T) == 4 ? 4 : 1)
     const int gc = min(Gp, bg1 - b0);
     if (Mbs) {
       // Bluestein ring: samples read per sub-transform, packed on the fly
-      const TIn *row = map + (size_t)b0 * npix;
-      auto input = [&](int k) {
+      auto input = [&](int c, int k) {
+        const TIn *row = map + (size_t)(b0 + c) * npix;
         const T a = load_as<T, TIn>(row + sN + k), b = equator ? (T)0 : load_as<T, TIn>(row + sS + k);
         return cmk<C>(a + b, a - b);
       };
-      ring_dft_bs4<T, NT>(tb, p, Mbs, bs_nb, buf, tq, n, b0 != bg0, input);
+      ring_dft_bs4<T, NT>(tb, p, Mbs, bs_nb, gc, buf, tq, n, b0 != bg0, input);
     } else {
       // rings -> LDS, packed as (f_N + f_S) + i (f_N - f_S); every load of the
       // pass is issued before the LDS writes
@@ -727,7 +747,7 @@ __global__ void __launch_bounds__(NT, sizeof(T) == 4 ? 4 : 1)
   const size_t npix = (size_t)tb.npix;
   const int Mbs = tb.rp_M[p];
   const int pad = Mbs == 0 && n >= kPadMin;  // Bluestein rings leave their DFT unpadded
-  const int Gp = Mbs ? 1 : G;
+  const int Gp = Mbs ? bs_channels<NT>(G, bs_nb, Mbs, n, tq_off) : G;
   int tid = threadIdx.x;
   // c_m = g_m exp(+i m phi0)
   auto phased = [&](const C *src, int m) {
@@ -794,12 +814,12 @@ __global__ void __launch_bounds__(NT, sizeof(T) == 4 ? 4 : 1)
     const C *gs = GS + sbase + (b0 - bg0);
     if (Mbs) {
       // Bluestein ring: folded values computed per sub-transform sample
-      auto input = [&](int k) {
+      auto input = [&](int c, int k) {
         C pn, ps, qn, qs;
-        fold_load(gn, gs, k, 0, pn, ps, qn, qs);
-        return fold_value(gn, gs, k, 0, pn, ps, qn, qs);
+        fold_load(gn, gs, k, c, pn, ps, qn, qs);
+        return fold_value(gn, gs, k, c, pn, ps, qn, qs);
       };
-      ring_dft_bs4<T, NT>(tb, p, Mbs, bs_nb, buf, tq, n, b0 != bg0, input);
+      ring_dft_bs4<T, NT>(tb, p, Mbs, bs_nb, gc, buf, tq, n, b0 != bg0, input);
     } else {
 #pragma unroll 1
       for (int j0 = tid; j0 < gc * n; j0 += kFoldUnroll * NT) {
