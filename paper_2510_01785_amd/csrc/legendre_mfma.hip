@@ -21,6 +21,9 @@ __device__ __forceinline__ f32x16 mfma32(float a, float b, f32x16 c) {
   return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
 }
 
+// Word 3 of a raw buffer resource on gfx9-family GPUs (untyped 32-bit
+// loads, no swizzle).
+constexpr int kBufferWord3 = 0x00020000;
 constexpr int kFwdWaves = 4;
 constexpr int kSubL = 64;       // l's per LDS sub-tile (two per block)
 constexpr int kTileRS = 64 + 4; // row stride of the LDS tile in floats
@@ -75,17 +78,30 @@ __global__ void __launch_bounds__(256)
     if (__all(t0 >= kBlockL)) continue;  // no ring of this slice is active here
     const double2 v = qok ? tb.ck_v[(size_t)item * Rp + q] : make_double2(0.0, 0.0);
     const double z = qok ? tb.rp_z[q] : 0.0;
+    // last start offset of the wave: later groups need no injection selects
+    int tx = t0 < kBlockL ? t0 : -1;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) tx = max(tx, __shfl_xor(tx, o));
+    const int tlast = __builtin_amdgcn_readfirstlane(tx);
     // B operands: K-step s pairs ring c0+64w+s (lanes < 32) with ring +32 (lanes >= 32)
     float xe[32], xo[32];
     const int rw = c0 + w * 64;  // first ring of this wave's slice (uniform)
     if (fast_rows && rw + 64 <= Rp) {
       // uniform row address per step, one 32-bit lane offset (half, column)
-      const unsigned voff = (unsigned)(h * 32 * rowf + colc);
+      // buffer loads: one resource per slice (uniform base), the lane's byte
+      // offset in a VGPR and the step's row offset in an SGPR, so no per-load
+      // vector address arithmetic (offsets < 2^32 by fast_rows)
+      const unsigned voff = (unsigned)(h * 32 * rowf + colc) * 4u;
       const size_t o0 = ((size_t)rw * M + m) * B * 2 + (size_t)b0 * 2;
+      const __amdgpu_buffer_rsrc_t re = __builtin_amdgcn_make_buffer_rsrc(
+          const_cast<float *>(xe_f + o0), 0, 0xffffffff, kBufferWord3);
+      const __amdgpu_buffer_rsrc_t ro = __builtin_amdgcn_make_buffer_rsrc(
+          const_cast<float *>(xo_f + o0), 0, 0xffffffff, kBufferWord3);
 #pragma unroll
       for (int s = 0; s < 32; ++s) {
-        xe[s] = xe_f[o0 + s * rowf + voff];
-        xo[s] = xo_f[o0 + s * rowf + voff];
+        const unsigned so = (unsigned)(s * rowf) * 4u;
+        xe[s] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(re, voff, so, 0));
+        xo[s] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(ro, voff, so, 0));
       }
     } else {
       // rings beyond the last pair read the last pair (their lambda is zero)
@@ -100,28 +116,36 @@ __global__ void __launch_bounds__(256)
     double prv = 0.0, cur = 0.0;
 #pragma unroll
     for (int hb = 0; hb < 2; ++hb) {
-      // recurrence: 64 steps, one lambda per lane per step into the tile.
-      // Coefficients are uniform (scalar loads, index clamped to lmax);
-      // steps past lmax produce values that are masked to zero.
+      // recurrence: 64 steps, one lambda per lane per step into the tile
 #pragma unroll 1
       for (int t8 = 0; t8 < kSubL / 8; ++t8) {
         const int tb8 = hb * kSubL + t8 * 8;
         double Ac[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) Ac[u] = sA[tb8 + u];
+        // rows l > lmax only feed output rows that are never stored
+        if (tb8 <= tlast) {  // uniform: some ring starts in this group
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          const double nx = fma(Ac[u] * z, cur, -prv);
-          if (u == 0) {
-            const bool inj = (tb8 == t0);
-            prv = inj ? v.x : cur;
-            cur = inj ? v.y : nx;
-          } else {
+          for (int u = 0; u < 8; ++u) {
+            const double nx = fma(Ac[u] * z, cur, -prv);
+            if (u == 0) {
+              const bool inj = (tb8 == t0);
+              prv = inj ? v.x : cur;
+              cur = inj ? v.y : nx;
+            } else {
+              prv = cur;
+              cur = nx;
+            }
+            tw[(t8 * 8 + u) * kTileRS + j] = (float)cur;
+          }
+        } else {
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const double nx = fma(Ac[u] * z, cur, -prv);
             prv = cur;
             cur = nx;
+            tw[(t8 * 8 + u) * kTileRS + j] = (float)cur;
           }
-          // rows l > lmax only feed output rows that are never stored
-          tw[(t8 * 8 + u) * kTileRS + j] = (float)cur;
         }
       }
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -234,13 +258,18 @@ __global__ void __launch_bounds__(64)
   const double z = pok ? tb.rp_z[p] : 0.0;
   const int ls = pok ? tb.seed_l[(size_t)m * Rp + p] : L + 1;
   const double2 sd = pok ? tb.seed_v[(size_t)m * Rp + p] : make_double2(0.0, 0.0);
-  // first l any ring of each 32-ring half needs (aligned to m + 8j like every seed)
-  int wh = ls;
+  // first l any ring of each 32-ring half needs (aligned to m + 8j like every
+  // seed), and the last seed of the wave (after it no ring starts: steps
+  // without the injection selects)
+  int wh = ls, wx = pok && ls <= L ? ls : -1;
 #pragma unroll
   for (int o = 1; o < 32; o <<= 1) wh = min(wh, __shfl_xor(wh, o));
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) wx = max(wx, __shfl_xor(wx, o));
   const int wl0 = __builtin_amdgcn_readfirstlane(wh);
   const int wl1 = __builtin_amdgcn_readfirstlane(__shfl(wh, 32));
   const int wl = min(wl0, wl1);
+  const int wlast = __builtin_amdgcn_readfirstlane(wx);
   f32x16 acc[4];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
@@ -259,16 +288,22 @@ __global__ void __launch_bounds__(64)
   // of the group starting at lq are rows lq + 2h + {0, 1, 4, 5}.  Rows past
   // lmax (at most 7, inside the padded coefficient workspace) are read and
   // then zeroed with their lambda in the last group.
+  // Buffer loads: the slab's base in the resource, the lane's offsets in
+  // VGPRs and the group's row offset in an SGPR (no per-load vector address
+  // arithmetic); the slab of one m is below 2^32 bytes for any supported
+  // (lmax, batch) that fits the device.
   const float *ag = reinterpret_cast<const float *>(ALMT) + ((size_t)aoff * B + b0) * 2;
-  const int arow = 2 * B;
-  const unsigned vo0 = (unsigned)(2 * h * arow + colc), vo1 = vo0 + arow, vo4 = vo0 + 4 * arow,
-                 vo5 = vo0 + 5 * arow;
+  const unsigned arow = 2u * (unsigned)B;
+  const unsigned vo0 = (2u * h * arow + colc) * 4u, vo1 = vo0 + arow * 4u, vo4 = vo0 + 16u * arow,
+                 vo5 = vo0 + 20u * arow;
+  const __amdgpu_buffer_rsrc_t ar = __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(ag), 0, 0xffffffff,
+                                                                       kBufferWord3);
   auto fetchB = [&](int lq, float (&bv)[4]) {
-    const float *rp = ag + (size_t)lq * arow;
-    bv[0] = rp[vo0];
-    bv[1] = rp[vo1];
-    bv[2] = rp[vo4];
-    bv[3] = rp[vo5];
+    const unsigned so = (unsigned)lq * arow * 4u;
+    bv[0] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(ar, vo0, so, 0));
+    bv[1] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(ar, vo1, so, 0));
+    bv[2] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(ar, vo4, so, 0));
+    bv[3] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(ar, vo5, so, 0));
   };
   double prv = 0.0, cur = 0.0;
   float bn[4];
@@ -290,18 +325,28 @@ __global__ void __launch_bounds__(64)
       for (int u = 0; u < 8; ++u) an[u] = Ag[lq + 8 + u];
     }
     float lam[8];
+    if (lq <= wlast) {  // uniform: some ring starts at lq
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const double nx = fma(ac[u] * z, cur, -prv);
-      if (u == 0) {
-        const bool inj = (lq == ls);
-        prv = inj ? sd.x : cur;
-        cur = inj ? sd.y : nx;
-      } else {
+      for (int u = 0; u < 8; ++u) {
+        const double nx = fma(ac[u] * z, cur, -prv);
+        if (u == 0) {
+          const bool inj = (lq == ls);
+          prv = inj ? sd.x : cur;
+          cur = inj ? sd.y : nx;
+        } else {
+          prv = cur;
+          cur = nx;
+        }
+        lam[u] = (float)cur;
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const double nx = fma(ac[u] * z, cur, -prv);
         prv = cur;
         cur = nx;
+        lam[u] = (float)cur;
       }
-      lam[u] = (float)cur;
     }
     float bb[4] = {bc[0], bc[1], bc[2], bc[3]};
     if (lq + 7 > L) {  // last group: l beyond lmax contributes nothing
