@@ -566,6 +566,29 @@ __device__ __forceinline__ int bs_channels(int G, int nb, int M, int n, int buf_
   return max(g, 1);
 }
 
+// Ring phase exp(+-i m phi0): phi0 = pi num / den with num = 0, or num = 1
+// and den = n, the ring length (HEALPix caps: pi/(4i); belt: pi/(4 nside) on
+// every other ring).  From the ring's root table w^q = exp(-2 pi i q / n):
+// for m mod 2n = 2q + b, exp(i pi m / n) = conj(w^q) h^b with h = exp(i pi/n)
+// (a lookup and one product instead of a sine and cosine).  mm = m mod 2n.
+template <typename T> struct RingPhase {
+  const cplx<T> *w;  // roots of the ring length
+  cplx<T> h;         // exp(i pi / n)
+  bool on;           // num = 1
+  __device__ __forceinline__ cplx<T> plus(int mm) const {  // exp(+i m phi0)
+    using C = cplx<T>;
+    if (!on) return cmk<C>(1, 0);
+    const C r = cconj(w[mm >> 1]);
+    const C hb = (mm & 1) ? h : cmk<C>(1, 0);
+    return cmul(r, hb);
+  }
+  __device__ __forceinline__ cplx<T> minus(int mm) const { return cconj(plus(mm)); }  // exp(-i m phi0)
+};
+template <typename T>
+__device__ __forceinline__ RingPhase<T> ring_phase(const Tables &tb, int n, int num) {
+  return RingPhase<T>{TabOf<T>::roots(tb) + roots_offset(n >> 2), phase_pi<T>(1, n, (T)1), num != 0};
+}
+
 // Workgroup -> (ring pair, channel slice).  A ring pair's channels are split
 // into ceil(B / G) slices of G; the slices of one ring pair get consecutive
 // workgroup ids of one XCD (ids x, x+8, x+16, ... go to XCD x), so the
@@ -637,12 +660,13 @@ __global__ void __launch_bounds__(NT, sizeof(T) == 4 ? 4 : 1)
   const bool equator = (sN == sS);
   const int L = tb.lmax, M = L + 1;
   const T w = (T)(wtab ? wtab[p] * wscale : wscale);
-  const int num = tb.rp_p0n[p], den = tb.rp_p0d[p];
+  const int num = tb.rp_p0n[p];  // phase numerator (the denominator is n when num = 1)
   const size_t npix = (size_t)tb.npix;
   const int Mbs = tb.rp_M[p];
   const int pad = Mbs == 0 && n >= kPadMin;  // Bluestein rings leave their DFT unpadded
   const int Gp = Mbs ? bs_channels<NT>(G, bs_nb, Mbs, n, tq_off) : G;
   const int nq = n >> 2;  // quads of pixels per ring
+  const RingPhase<T> rph = ring_phase<T>(tb, n, num);
   const int tid = threadIdx.x;
 #pragma unroll 1
   for (int b0 = bg0; b0 < bg1; b0 += Gp) {
@@ -691,10 +715,10 @@ __global__ void __launch_bounds__(NT, sizeof(T) == 4 ? 4 : 1)
     const size_t obase = (size_t)p * M * B + b0;
     const bool pairs = ((B | b0) & 1) == 0;  // channel pairs start 16-byte aligned
     for (int m = tid; m < M; m += NT) {
-      const int k = m < n ? m : m % n;
+      const int mm = m < 2 * n ? m : m % (2 * n);  // m mod 2n
+      const int k = mm < n ? mm : mm - n;          // m mod n
       const int kc = (k == 0) ? 0 : n - k;
-      const int red = (int)(((long long)m * num) % (2 * den));
-      C ph = phase_pi<T>(red, den, (T)-1);
+      C ph = rph.minus(mm);
       ph.x *= w;
       ph.y *= w;
       C *xe = XE + obase + (size_t)m * B;
@@ -743,17 +767,15 @@ __global__ void __launch_bounds__(NT, sizeof(T) == 4 ? 4 : 1)
   const int sN = tb.rp_sN[p], sS = tb.rp_sS[p];
   const bool equator = (sN == sS);
   const int L = tb.lmax, M = L + 1;
-  const int num = tb.rp_p0n[p], den = tb.rp_p0d[p];
+  const int num = tb.rp_p0n[p];  // phase numerator (the denominator is n when num = 1)
   const size_t npix = (size_t)tb.npix;
   const int Mbs = tb.rp_M[p];
   const int pad = Mbs == 0 && n >= kPadMin;  // Bluestein rings leave their DFT unpadded
   const int Gp = Mbs ? bs_channels<NT>(G, bs_nb, Mbs, n, tq_off) : G;
   int tid = threadIdx.x;
-  // c_m = g_m exp(+i m phi0)
-  auto phased = [&](const C *src, int m) {
-    const int red = (int)(((long long)m * num) % (2 * den));
-    return cmul(src[(size_t)m * G], phase_pi<T>(red, den, (T)1));
-  };
+  // c_m = g_m exp(+i m phi0), mm = m mod 2n
+  const RingPhase<T> rph = ring_phase<T>(tb, n, num);
+  auto phased = [&](const C *src, int m, int mm) { return cmul(src[(size_t)m * G], rph.plus(mm)); };
   // this workgroup's channel slice [m][G] of the synthesis spectra
   const int ns = (B + G - 1) / G;
   const size_t sbase = ((size_t)p * ns + bg0 / G) * M * G;
@@ -776,10 +798,9 @@ __global__ void __launch_bounds__(NT, sizeof(T) == 4 ? 4 : 1)
   };
   auto fold_value = [&](const C *gn, const C *gs, int k, int c, C pn, C ps, C qn, C qs) {
     C cn = cmk<C>(0, 0), cs = cmk<C>(0, 0);
-    const int m1 = k, m2 = (k == 0) ? n : n - k;
+    const int m1 = k, m2 = (k == 0) ? n : n - k;  // both below 2n
     if (m1 < M) {
-      const int red = (int)(((long long)m1 * num) % (2 * den));
-      const C ph = phase_pi<T>(red, den, (T)1);
+      const C ph = rph.plus(m1);
       cn = cmul(pn, ph);
       cs = cmul(ps, ph);
       if (m1 == 0) {
@@ -788,18 +809,19 @@ __global__ void __launch_bounds__(NT, sizeof(T) == 4 ? 4 : 1)
       }
     }
     if (m2 < M) {
-      const int red = (int)(((long long)m2 * num) % (2 * den));
-      const C ph = phase_pi<T>(red, den, (T)1);
+      const C ph = rph.plus(m2);
       cn = cadd(cn, cconj(cmul(qn, ph)));
       cs = cadd(cs, cconj(cmul(qs, ph)));
     }
-    for (int m = m1 + n; m < M; m += n) {
-      cn = cadd(cn, phased(gn + c, m));
-      if (!equator) cs = cadd(cs, phased(gs + c, m));
+    // further aliases m + t n: m mod 2n alternates between m and m + n
+    for (int m = m1 + n, mm = m1 + n; m < M; m += n, mm = mm >= n ? mm - n : mm + n) {
+      cn = cadd(cn, phased(gn + c, m, mm));
+      if (!equator) cs = cadd(cs, phased(gs + c, m, mm));
     }
-    for (int m = m2 + n; m < M; m += n) {
-      cn = cadd(cn, cconj(phased(gn + c, m)));
-      if (!equator) cs = cadd(cs, cconj(phased(gs + c, m)));
+    for (int m = m2 + n, mm = m2 + n >= 2 * n ? m2 - n : m2 + n; m < M;
+         m += n, mm = mm >= n ? mm - n : mm + n) {
+      cn = cadd(cn, cconj(phased(gn + c, m, mm)));
+      if (!equator) cs = cadd(cs, cconj(phased(gs + c, m, mm)));
     }
     return cmk<C>(cn.x - cs.y, -(cn.y + cs.x));
   };
