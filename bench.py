@@ -49,6 +49,9 @@ def parse():
     ap.add_argument("--rate", type=float, default=200.0)
     ap.add_argument("--budget-gib", type=float, default=48.0)
     ap.add_argument("--slots", type=int, default=8)
+    ap.add_argument("--peaks", action="store_true",
+                    help="only measure the device's HBM copy bandwidth and GEMM (matrix-core) rates "
+                         "with torch library calls, print one JSON line and exit")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (5 times), "
                          "to calibrate HBM byte counters, and exit")
@@ -212,6 +215,43 @@ def run_serving(args):
     print(json.dumps(out), flush=True)
 
 
+def run_peaks():
+    """Measured counterparts of the published peaks: a 4 GiB device copy
+    (HBM read + write) and large GEMMs in FP32, FP64 and BF16 (library
+    kernels on the matrix cores), each the best of 5 timed runs."""
+    import torch
+    dev = torch.device("cuda:0")
+
+    def best(fn, reps=5):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1) / 1000.0)
+        return min(ts)
+    n = (4 << 30) // 4
+    src = torch.ones(n, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    t = best(lambda: dst.copy_(src))
+    out = {"hbm_copy_GBs": round(2 * 4 * n / t / 1e9, 1)}
+    del src, dst
+    for name, dt, k in (("fp32_gemm_TFs", torch.float32, 8192), ("fp64_gemm_TFs", torch.float64, 8192),
+                        ("bf16_gemm_TFs", torch.bfloat16, 16384)):
+        a = torch.randn(k, k, device=dev).to(dt)
+        b = torch.randn(k, k, device=dev).to(dt)
+        t = best(lambda: torch.matmul(a, b))
+        out[name] = round(2.0 * k ** 3 / t / 1e12, 1)
+        del a, b
+    out["published"] = {"hbm_GBs": PEAK["hbm_GBs"], "fp32_mfma_TFs": PEAK["fp32_mfma_TFs"],
+                        "fp64_mfma_TFs": 78.6, "bf16_mfma_TFs": 2500.0}
+    print(json.dumps(out), flush=True)
+
+
 def run_jacobi(args):
     """3-iteration refined analysis (Eq. (4)) of one map at Nside=2048,
     lmax=4095 (4 forward + 3 inverse transforms), FP64 or FP32; the field is a
@@ -285,6 +325,8 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"calibrate_copy_bytes": 4 * n, "copies": 5}))
         return
+    if args.peaks:
+        return run_peaks()
     if args.workload == "serving":
         return run_serving(args)
     if args.workload == "jacobi":
@@ -335,6 +377,13 @@ def main():
     prof = _lib.profile_read()
     lat = np.array([a.elapsed_time(b) for a, b in evs])
     print("[bench] timed %d steps in %.3f s" % (args.steps, wall), flush=True)
+    # accuracy of one analysis of the synthesised maps against the coefficients
+    # they were made from (quadrature error of Eq. (1) plus rounding)
+    a_chk = shtx.map2alm_raw(maps, lmax).to(alm0.dtype)
+    diff = (a_chk - alm0).abs()
+    roundtrip = {"rel_l2": float("%.3e" % (torch.linalg.vector_norm(a_chk - alm0) / torch.linalg.vector_norm(alm0)).item()),
+                 "rel_linf": float("%.3e" % (diff.max() / alm0.abs().max()).item())}
+    del a_chk, diff
 
     value = B * args.steps / wall
     ms_per_step = 1000.0 * wall / args.steps
@@ -401,6 +450,7 @@ def main():
                    "fields": "gaussian C_l=(l+10)^-2"},
         "stages_ms_per_call": {k: round(v["ms_per_call"], 4) for k, v in stages.items()},
         "roofline": roof,
+        "analysis_vs_input_alm": roundtrip,
     }
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", flush=True)
