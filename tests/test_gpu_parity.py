@@ -219,7 +219,8 @@ def test_loss_gradient_fd_nside16(shtx):
 
 
 @pytest.mark.parametrize("nside,lmax,batch,dtype,niter", [(32, 95, 2, torch.float64, 3), (16, 47, 1, torch.float64, 0),
-                                                          (32, 63, 17, torch.float32, 3)])
+                                                          (32, 63, 17, torch.float32, 3), (32, 95, 3, torch.float32, 2),
+                                                          (64, 191, 3, torch.float64, 1)])
 def test_jacobi_iteration_parity(shtx, nside, lmax, batch, dtype, niter):
     """Iterative refinement a <- a + A(f - S a) (Eq. (4)) through the library's
     one entry point, against the oracle's loop of plain transforms."""
