@@ -120,9 +120,18 @@ __global__ void __launch_bounds__(256)
 #pragma unroll 1
       for (int t8 = 0; t8 < kSubL / 8; ++t8) {
         const int tb8 = hb * kSubL + t8 * 8;
+        // the group's coefficients: one lane-uniform LDS address, four
+        // 16-byte reads at immediate offsets
+        int aaddr = tb8;
+        asm volatile("" : "+v"(aaddr));
+        const double2 *sA2 = reinterpret_cast<const double2 *>(sA + aaddr);
         double Ac[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) Ac[u] = sA[tb8 + u];
+        for (int u = 0; u < 4; ++u) {
+          const double2 a2 = sA2[u];
+          Ac[2 * u] = a2.x;
+          Ac[2 * u + 1] = a2.y;
+        }
         // rows l > lmax only feed output rows that are never stored
         if (tb8 <= tlast) {  // uniform: some ring starts in this group
 #pragma unroll
