@@ -144,19 +144,22 @@ template <typename C, int R> __device__ __forceinline__ void dftR(C (&u)[R]) {
   else dft2(u[0], u[1]);
 }
 
-// u[r] *= w^{r e} for r = 1..R-1 (e < N/R, so no exponent wraps).  Radix 16
-// takes w^e, w^2e, w^3e, w^4e, w^8e, w^12e from the table and forms the other
-// nine as one product each; radix 8 forms w^5e..w^7e from w^4e.
+// u[r] *= w^{r e} for r = 1..R-1 (e < N/R, so no exponent wraps).  One
+// table lookup, w^e; the other powers are products (radix 16: w^2e, w^3e,
+// w^4e, w^8e, w^12e by squaring and one product each, then the nine
+// w^{(r1 + 4 r2) e} = w^{4 r2 e} w^{r1 e}).  A power is at most six roundings
+// from the table value.
 template <typename C, int R> __device__ __forceinline__ void twiddle(C (&u)[R], const C *tq, int e, int lq) {
+  const C w1 = tw_oct(tq, e, lq);
   if constexpr (R == 2) {
-    u[1] = cmul(u[1], tw_oct(tq, e, lq));
+    u[1] = cmul(u[1], w1);
   } else if constexpr (R == 4) {
-    u[1] = cmul(u[1], tw_oct(tq, e, lq));
-    u[2] = cmul(u[2], tw_oct(tq, 2 * e, lq));
-    u[3] = cmul(u[3], tw_oct(tq, 3 * e, lq));
+    const C w2 = cmul(w1, w1);
+    u[1] = cmul(u[1], w1);
+    u[2] = cmul(u[2], w2);
+    u[3] = cmul(u[3], cmul(w2, w1));
   } else if constexpr (R == 8) {
-    const C w1 = tw_oct(tq, e, lq), w2 = tw_oct(tq, 2 * e, lq), w3 = tw_oct(tq, 3 * e, lq);
-    const C w4 = tw_oct(tq, 4 * e, lq);
+    const C w2 = cmul(w1, w1), w3 = cmul(w2, w1), w4 = cmul(w2, w2);
     u[1] = cmul(u[1], w1);
     u[2] = cmul(u[2], w2);
     u[3] = cmul(u[3], w3);
@@ -166,12 +169,12 @@ template <typename C, int R> __device__ __forceinline__ void twiddle(C (&u)[R], 
     u[7] = cmul(u[7], cmul(w4, w3));
   } else {
     C lo[4], hi[4];
-    lo[1] = tw_oct(tq, e, lq);
-    lo[2] = tw_oct(tq, 2 * e, lq);
-    lo[3] = tw_oct(tq, 3 * e, lq);
-    hi[1] = tw_oct(tq, 4 * e, lq);
-    hi[2] = tw_oct(tq, 8 * e, lq);
-    hi[3] = tw_oct(tq, 12 * e, lq);
+    lo[1] = w1;
+    lo[2] = cmul(w1, w1);
+    lo[3] = cmul(lo[2], w1);
+    hi[1] = cmul(lo[2], lo[2]);
+    hi[2] = cmul(hi[1], hi[1]);
+    hi[3] = cmul(hi[2], hi[1]);
 #pragma unroll
     for (int r1 = 1; r1 < 4; ++r1) u[r1] = cmul(u[r1], lo[r1]);
 #pragma unroll
@@ -215,9 +218,13 @@ __device__ __forceinline__ void stage_p2(cplx<T> *buf, int logn, int G, int logp
   const int Tq = 1 << logTq;
   const int nb = G << logTq;
   const int p = 1 << logp;
-  const int cs = lstride(n, pad);
-  const int is = lstride(Tq, pad);
-  const int os = logp == 0 ? 1 : lstride(p, pad);
+  int cs = __builtin_amdgcn_readfirstlane(lstride(n, pad));
+  int is = __builtin_amdgcn_readfirstlane(lstride(Tq, pad));
+  int os = __builtin_amdgcn_readfirstlane(logp == 0 ? 1 : lstride(p, pad));
+  // Opaque strides: the R offsets r * is and q * os are formed here, per
+  // stage (hoisted to the kernel entry they occupy ~30 scalar registers per
+  // stage form and spill).
+  asm volatile("" : "+s"(cs), "+s"(is), "+s"(os));
   // Opaque copy of the thread index: keeps the per-butterfly index arithmetic
   // inside the stage (hoisted out of the stage loop it would stay live over
   // the whole transform and spill).
