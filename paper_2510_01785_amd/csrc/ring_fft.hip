@@ -803,8 +803,12 @@ __global__ void __launch_bounds__(NT, sizeof(T) == 4 ? 4 : 1)
       if (!equator) qs = gs[(size_t)m2 * G + c];
     }
   };
-  auto fold_value = [&](const C *gn, const C *gs, int k, int c, C pn, C ps, C qn, C qs) {
-    C cn = cmk<C>(0, 0), cs = cmk<C>(0, 0);
+  // C_N, C_S at k (the sums over the aliases m = +-k mod n of g_m exp(i m phi0),
+  // the negative ones conjugated).  At n - k the sums are the conjugates: the
+  // aliases of +k are those of -(n - k) and vice versa.
+  auto fold_sums = [&](const C *gn, const C *gs, int k, int c, C pn, C ps, C qn, C qs, C &cn, C &cs) {
+    cn = cmk<C>(0, 0);
+    cs = cmk<C>(0, 0);
     const int m1 = k, m2 = (k == 0) ? n : n - k;  // both below 2n
     if (m1 < M) {
       const C ph = rph.plus(m1);
@@ -830,6 +834,10 @@ __global__ void __launch_bounds__(NT, sizeof(T) == 4 ? 4 : 1)
       cn = cadd(cn, cconj(phased(gn + c, m, mm)));
       if (!equator) cs = cadd(cs, cconj(phased(gs + c, m, mm)));
     }
+  };
+  auto fold_value = [&](const C *gn, const C *gs, int k, int c, C pn, C ps, C qn, C qs) {
+    C cn, cs;
+    fold_sums(gn, gs, k, c, pn, ps, qn, qs, cn, cs);
     return cmk<C>(cn.x - cs.y, -(cn.y + cs.x));
   };
 #pragma unroll 1
@@ -850,21 +858,27 @@ __global__ void __launch_bounds__(NT, sizeof(T) == 4 ? 4 : 1)
       };
       ring_dft_bs4<T, NT>(tb, p, Mbs, bs_nb, gc, buf, tq, n, b0 != bg0, input);
     } else {
+      // k = 0..n/2; each item also writes k' = n - k (conjugate sums)
+      const int nk = gc * ((n >> 1) + 1);
 #pragma unroll 1
-      for (int j0 = tid; j0 < gc * n; j0 += kFoldUnroll * NT) {
+      for (int j0 = tid; j0 < nk; j0 += kFoldUnroll * NT) {
         C pn[kFoldUnroll], ps[kFoldUnroll], qn[kFoldUnroll], qs[kFoldUnroll];
 #pragma unroll
         for (int u = 0; u < kFoldUnroll; ++u) {
           const int j = j0 + u * NT;
           const int k = j / gc, c = j - k * gc;  // channel fastest: adjacent channels adjacent in memory
-          if (j < gc * n) fold_load(gn, gs, k, c, pn[u], ps[u], qn[u], qs[u]);
+          if (j < nk) fold_load(gn, gs, k, c, pn[u], ps[u], qn[u], qs[u]);
         }
 #pragma unroll
         for (int u = 0; u < kFoldUnroll; ++u) {
           const int j = j0 + u * NT;
-          if (j >= gc * n) continue;
+          if (j >= nk) continue;
           const int k = j / gc, c = j - k * gc;
-          buf[lidx(c * n + k, pad)] = fold_value(gn, gs, k, c, pn[u], ps[u], qn[u], qs[u]);
+          C cn, cs;
+          fold_sums(gn, gs, k, c, pn[u], ps[u], qn[u], qs[u], cn, cs);
+          // conj(h) at k and at n - k, h = C_N + i C_S
+          buf[lidx(c * n + k, pad)] = cmk<C>(cn.x - cs.y, -(cn.y + cs.x));
+          if (k != 0 && 2 * k != n) buf[lidx(c * n + n - k, pad)] = cmk<C>(cn.x + cs.y, cn.y - cs.x);
         }
       }
       __syncthreads();
