@@ -191,12 +191,43 @@ template <typename C, int R> __device__ __forceinline__ void twiddle(C (&u)[R], 
 enum FuseIn { kInPlain = 0, kInChirp = 1 };        // x_j * c_j for j < nvalid, 0 beyond
 enum FuseOut { kOutPlain = 0, kOutBhat = 1, kOutChirp = 2 };  // conj(y * bhat) / c_o * conj(y) / M
 
+// The tables are read through buffer resources: a 32-bit element offset per
+// load (no 64-bit address arithmetic), and a read at or beyond the resource's
+// size returns zero instead of touching memory, so the loads need no bounds
+// branch.
+constexpr int kBufWord3 = 0x00020000;  // untyped 32-bit data, no swizzle
 template <typename T> struct Fuse {
-  const cplx<T> *chirp;
-  const cplx<T> *bhat;
+  __amdgpu_buffer_rsrc_t chirp;  // c_j for j < nvalid
+  __amdgpu_buffer_rsrc_t bhat;   // M values
   int nvalid;
   T scale;
 };
+// A workgroup-uniform pointer, made visibly uniform (a resource built from a
+// value the compiler takes as divergent costs a loop over lanes per load).
+template <typename P> __device__ __forceinline__ P *uniform_ptr(P *p) {
+  const unsigned long long a = reinterpret_cast<unsigned long long>(p);
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)a);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(a >> 32));
+  return reinterpret_cast<P *>(((unsigned long long)hi << 32) | lo);
+}
+template <typename T>
+__device__ __forceinline__ Fuse<T> make_fuse(const cplx<T> *chirp, int nvalid, const cplx<T> *bhat, int M, T scale) {
+  nvalid = __builtin_amdgcn_readfirstlane(nvalid);
+  M = __builtin_amdgcn_readfirstlane(M);
+  return Fuse<T>{__builtin_amdgcn_make_buffer_rsrc(const_cast<cplx<T> *>(uniform_ptr(chirp)), 0,
+                                                   nvalid * (int)sizeof(cplx<T>), kBufWord3),
+                 __builtin_amdgcn_make_buffer_rsrc(const_cast<cplx<T> *>(uniform_ptr(bhat)), 0,
+                                                   M * (int)sizeof(cplx<T>), kBufWord3),
+                 nvalid, scale};
+}
+__device__ __forceinline__ float2 tab_load(__amdgpu_buffer_rsrc_t r, int e, float2) {
+  const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, e * 8, 0, 0);
+  return make_float2(__uint_as_float(v[0]), __uint_as_float(v[1]));
+}
+__device__ __forceinline__ double2 tab_load(__amdgpu_buffer_rsrc_t r, int e, double2) {
+  const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, e * 16, 0, 0);
+  return make_double2(__hiloint2double(v[1], v[0]), __hiloint2double(v[3], v[2]));
+}
 
 // Stockham stage of power-of-two radix R on G channels of length n = 2^logn
 // with span p = 2^logp: butterfly i of channel c reads x[i + r n/R], twiddles
@@ -243,7 +274,10 @@ __device__ __forceinline__ void stage_p2(cplx<T> *buf, int logn, int G, int logp
 #pragma unroll
         for (int r = 0; r < R; ++r) {
           const int j = i + r * Tq;
-          v[s][r] = (j < fz.nvalid) ? cmul(v[s][r], fz.chirp[j]) : cmk<C>(0, 0);
+          // zero padding: the buffer beyond nvalid holds no samples (a select,
+          // not a product: the LDS there is unset); the load itself reads 0 there
+          const C cj = tab_load(fz.chirp, j, C{});
+          v[s][r] = (j < fz.nvalid) ? cmul(v[s][r], cj) : cmk<C>(0, 0);
         }
       }
       if (logp > 0) twiddle<C, R>(v[s], tq, (i & (p - 1)) << (logTq - logp), lq);
@@ -264,13 +298,14 @@ __device__ __forceinline__ void stage_p2(cplx<T> *buf, int logn, int G, int logp
         for (int q = 0; q < R; ++q) buf[ob + q * os] = v[s][q];
       } else if (fout == kOutBhat) {
 #pragma unroll
-        for (int q = 0; q < R; ++q) buf[ob + q * os] = cconj(cmul(v[s][q], fz.bhat[o0 + q * p]));
+        for (int q = 0; q < R; ++q) buf[ob + q * os] = cconj(cmul(v[s][q], tab_load(fz.bhat, o0 + q * p, C{})));
       } else {
 #pragma unroll
         for (int q = 0; q < R; ++q) {
           const int o = o0 + q * p;
           const C cv = cconj(v[s][q]);
-          if (o < fz.nvalid) buf[ob + q * os] = cmul(fz.chirp[o], cmk<C>(cv.x * fz.scale, cv.y * fz.scale));
+          const C ch = tab_load(fz.chirp, o, C{});
+          if (o < fz.nvalid) buf[ob + q * os] = cmul(ch, cmk<C>(cv.x * fz.scale, cv.y * fz.scale));
         }
       }
     }
@@ -440,7 +475,7 @@ __device__ __forceinline__ void ring_dft(const Tables &tb, cplx<T> *buf, cplx<T>
     load_octant<T, NT>(tq, TabOf<T>::roots(tb) + roots_offset(n >> 2), n, 1);
     __syncthreads();
   }
-  const Fuse<T> fz{nullptr, nullptr, n, (T)1};
+  const Fuse<T> fz = make_fuse<T>(nullptr, 0, nullptr, 0, (T)1);
   fft_p2<T, NT>(buf, __builtin_ctz(n), gc, pad, tq, fz, kInPlain, kOutPlain);
 }
 
@@ -485,7 +520,8 @@ __device__ __forceinline__ void ring_dft_bs4(const Tables &tb, int p, int M, int
     load_octant<T, NT>(tq, TabOf<T>::rootsP(tb), M, tb.mmax_bs / M);
     __syncthreads();
   }
-  const Fuse<T> fz{TabOf<T>::chirp(tb) + roots_offset(i), TabOf<T>::bhat(tb) + tb.rp_bsoff[p], i, (T)1 / (T)M};
+  const Fuse<T> fz = make_fuse<T>(TabOf<T>::chirp(tb) + roots_offset(i), i, TabOf<T>::bhat(tb) + tb.rp_bsoff[p], M,
+                                  (T)1 / (T)M);
   const int logM = __builtin_ctz(M);
   // opaque copies of the thread index per phase (as in stage_p2): index
   // arithmetic hoisted out of the pass loop would stay live and spill
