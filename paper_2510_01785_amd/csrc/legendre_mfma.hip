@@ -78,11 +78,16 @@ __global__ void __launch_bounds__(256)
     if (__all(t0 >= kBlockL)) continue;  // no ring of this slice is active here
     const double2 v = qok ? tb.ck_v[(size_t)item * Rp + q] : make_double2(0.0, 0.0);
     const double z = qok ? tb.rp_z[q] : 0.0;
-    // last start offset of the wave: later groups need no injection selects
-    int tx = t0 < kBlockL ? t0 : -1;
+    // last start offset of the wave: later groups need no injection selects;
+    // first start offset: a half block before it holds only zero lambdas
+    int tx = t0 < kBlockL ? t0 : -1, tn = t0;
 #pragma unroll
-    for (int o = 1; o < 64; o <<= 1) tx = max(tx, __shfl_xor(tx, o));
+    for (int o = 1; o < 64; o <<= 1) {
+      tx = max(tx, __shfl_xor(tx, o));
+      tn = min(tn, __shfl_xor(tn, o));
+    }
     const int tlast = __builtin_amdgcn_readfirstlane(tx);
+    const int tfirst = __builtin_amdgcn_readfirstlane(tn);
     // B operands: K-step s pairs ring c0+64w+s (lanes < 32) with ring +32 (lanes >= 32)
     float xe[32], xo[32];
     const int rw = c0 + w * 64;  // first ring of this wave's slice (uniform)
@@ -116,6 +121,11 @@ __global__ void __launch_bounds__(256)
     double prv = 0.0, cur = 0.0;
 #pragma unroll
     for (int hb = 0; hb < 2; ++hb) {
+      // half blocks with no lambda: every ring of the wave starts after it
+      // (the recurrence state stays zero until its start), or every l of it
+      // is beyond lmax (output rows that are never stored)
+      if (hb == 0 && tfirst >= kSubL) continue;
+      if (hb == 1 && l0 + kSubL > L) continue;
       // recurrence: 64 steps, one lambda per lane per step into the tile
 #pragma unroll 1
       for (int t8 = 0; t8 < kSubL / 8; ++t8) {
