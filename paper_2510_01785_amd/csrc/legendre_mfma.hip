@@ -71,13 +71,27 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc[a][r] = 0.f;
 
-  for (int c0 = 0; c0 < Rp; c0 += 64 * kFwdWaves) {
-    const int q = c0 + w * 64 + j;  // this lane's ring for the recurrence
+  // this lane's ring per 256-ring chunk: recurrence start (kBlockL: not
+  // active in this block), checkpoint and z, fetched one chunk ahead
+  auto fetch_ring = [&](int q, int &t0, double2 &v, double &z) {
     const bool qok = q < Rp;
-    const int t0 = qok ? (int)tb.ck_t[(size_t)item * Rp + q] : kBlockL;
+    t0 = qok ? (int)tb.ck_t[(size_t)item * Rp + q] : kBlockL;
+    v = qok ? tb.ck_v[(size_t)item * Rp + q] : make_double2(0.0, 0.0);
+    z = qok ? tb.rp_z[q] : 0.0;
+  };
+  int t0n;
+  double2 vn;
+  double zn;
+  fetch_ring(w * 64 + j, t0n, vn, zn);
+  for (int c0 = 0; c0 < Rp; c0 += 64 * kFwdWaves) {
+    const int t0 = t0n;
+    const double2 v = vn;
+    const double z = zn;
+    // wait for this chunk's values here: the recurrence below then waits for
+    // no load, while the spectrum loads issued before it are in flight
+    asm volatile("" ::"v"(t0), "v"(v.x), "v"(v.y), "v"(z));
+    fetch_ring(c0 + 64 * kFwdWaves + w * 64 + j, t0n, vn, zn);
     if (__all(t0 >= kBlockL)) continue;  // no ring of this slice is active here
-    const double2 v = qok ? tb.ck_v[(size_t)item * Rp + q] : make_double2(0.0, 0.0);
-    const double z = qok ? tb.rp_z[q] : 0.0;
     // last start offset of the wave: later groups need no injection selects;
     // first start offset: a half block before it holds only zero lambdas
     int tx = t0 < kBlockL ? t0 : -1, tn = t0;
@@ -118,6 +132,9 @@ __global__ void __launch_bounds__(256)
         xo[s] = xo_f[o];
       }
     }
+    // issue the loads here, ahead of the recurrence (left alone, the compiler
+    // sinks them to their first use after it and their latency is exposed)
+    asm volatile("" ::: "memory");
     double prv = 0.0, cur = 0.0;
 #pragma unroll
     for (int hb = 0; hb < 2; ++hb) {
