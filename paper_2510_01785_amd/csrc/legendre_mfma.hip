@@ -342,24 +342,22 @@ __global__ void __launch_bounds__(64)
     bv[3] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(ar, vo5, so, 0));
   };
   double prv = 0.0, cur = 0.0;
-  float bn[4];
-  double an[8];  // A_l of the next group (scalar registers)
-  if (wl <= L) {
-    fetchB(wl, bn);
+  // one group of 8 steps from l = lq with its operands bc (B) and ac (A_l);
+  // the next group's operands go to bn, an (the last group re-reads its own
+  // rows: every group issues the same loads, so the waits count exactly).
+  // Two register sets alternate: no copies, and a group waits only for the
+  // loads issued one group earlier (scalar loads complete out of order, so a
+  // wait for one is a wait for all: the next ones go after this group's).
+  auto group = [&](int lq, const float (&bc)[4], const double (&ac)[8], float (&bn)[4], double (&an)[8]) {
+    const int ln = lq + 8 <= L ? lq + 8 : lq;
+    fetchB(ln, bn);
+    // the next group's scalar loads take an address that is known only
+    // once this group's A_l have arrived, so they are issued after that wait
+    // (and a group ahead of their own)
+    int la = ln;
+    asm volatile("" : "+s"(la) : "s"(ac[7]));
 #pragma unroll
-    for (int u = 0; u < 8; ++u) an[u] = Ag[wl + u];
-  }
-#pragma unroll 1
-  for (int lq = wl; lq <= L; lq += 8) {
-    const float bc[4] = {bn[0], bn[1], bn[2], bn[3]};
-    double ac[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) ac[u] = an[u];
-    if (lq + 8 <= L) {  // next group's operands in flight (rows < lmax + 8)
-      fetchB(lq + 8, bn);
-#pragma unroll
-      for (int u = 0; u < 8; ++u) an[u] = Ag[lq + 8 + u];
-    }
+    for (int u = 0; u < 8; ++u) an[u] = Ag[la + u];
     float lam[8];
     if (lq <= wlast) {  // uniform: some ring starts at lq
 #pragma unroll
@@ -411,6 +409,19 @@ __global__ void __launch_bounds__(64)
       acc[2] = mfma32(e1hi, bb[2], acc[2]);
       acc[3] = mfma32(o1hi, bb[3], acc[3]);
     }
+  };
+  float bA[4], bB[4];
+  double aA[8], aB[8];  // A_l of the groups (scalar registers)
+  if (wl <= L) {
+    fetchB(wl, bA);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) aA[u] = Ag[wl + u];
+  }
+#pragma unroll 1
+  for (int lq = wl; lq <= L; lq += 16) {
+    group(lq, bA, aA, bB, aB);
+    if (lq + 8 > L) break;
+    group(lq + 8, bB, aB, bA, aA);
   }
   if (!colok) return;
   float *gn = reinterpret_cast<float *>(GN);
