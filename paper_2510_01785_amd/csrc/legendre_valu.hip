@@ -27,20 +27,24 @@ namespace shtx {
 // partial sums of every (l, channel) are added through LDS, scaled by c_lm
 // and the entry point's factor, and written (or added) to the caller's layout
 // alm[b][idx(l, m)], Im = 0 for m = 0.
-template <typename T> struct FwdValuShape {
-  static constexpr int kSlots = sizeof(T) == 8 ? 16 : 32;  // (step, channel) slots per transpose
-  static constexpr int kRS = 65;                           // tile row stride in complex elements
+template <typename T, int BG> struct FwdValuShape {
+  // (step, channel) slots per transpose: 16, or 32 for FP32 groups of 4
+  // channels (whose final reduction needs the larger tile)
+  static constexpr int kSlots = (sizeof(T) == 4 && BG == 4) ? 32 : 16;
+  static constexpr int kRS = 65;  // tile row stride in complex elements
+  // waves per SIMD the registers are sized for: a 66.5 KB tile (FP64, or
+  // FP32 with 32 slots) allows two workgroups per CU, the 33 KB FP32 one three
+  static constexpr int kWaves = (sizeof(T) == 4 && kSlots == 16) ? 3 : 2;
 };
 
-// The LDS tile allows two workgroups (8 waves) per CU: the compiler may use
-// the registers of two waves per SIMD (loads kept in flight).
 template <typename T, int BG, int R>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
+__global__ void __launch_bounds__(256)
+    __attribute__((amdgpu_waves_per_eu(FwdValuShape<T, BG>::kWaves, FwdValuShape<T, BG>::kWaves)))
     k_legendre_fwd_valu(Tables tb, int B, int b0, const cplx<T> *__restrict__ XE, const cplx<T> *__restrict__ XO,
                         cplx<T> *__restrict__ alm, T f0, T fm, int accum) {
   using C = cplx<T>;
   constexpr int NW = 4;
-  constexpr int SLOTS = FwdValuShape<T>::kSlots, RS = FwdValuShape<T>::kRS;
+  constexpr int SLOTS = FwdValuShape<T, BG>::kSlots, RS = FwdValuShape<T, BG>::kRS;
   constexpr int SL = SLOTS / BG;     // steps per transpose
   constexpr int H = 64 / SLOTS;      // lane groups that share a slot
   constexpr int NG = kBlockL / SL;   // transposes per block
