@@ -16,6 +16,9 @@ the pins):
   sht.jacobi_map2alm          pinned (composition of pinned transforms; residual
                               decrease)
   sht.spectral_loss(_grad)    pinned (finite differences)
+  nested.*                    pinned (Nside-1 identity with the base-pixel
+                              geometry, bijection, south/east/west/north
+                              sub-pixels against the RING geometry)
 """
-from . import geometry, legendre, sht  # noqa: F401
+from . import geometry, legendre, nested, sht  # noqa: F401
 from ._clib import build  # noqa: F401
