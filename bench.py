@@ -41,10 +41,11 @@ def parse():
     ap.add_argument("--dtype", default="f32", choices=["f32", "f64", "bf16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-nside", type=int, default=None)
-    ap.add_argument("--workload", default="sht", choices=["sht", "serving", "jacobi"],
+    ap.add_argument("--workload", default="sht", choices=["sht", "serving", "jacobi", "reorder"],
                     help="sht: forward+inverse throughput (default); serving: Poisson trace of mixed "
                          "requests through the serving loop vs one at a time; jacobi: 3-iteration "
-                         "refined analysis at Nside=2048, lmax=4095, one map")
+                         "refined analysis at Nside=2048, lmax=4095, one map; reorder: RING <-> NESTED "
+                         "pixel order conversion of --batch maps at --nside")
     ap.add_argument("--requests", type=int, default=2000)
     ap.add_argument("--rate", type=float, default=200.0)
     ap.add_argument("--budget-gib", type=float, default=48.0)
@@ -309,6 +310,67 @@ def run_jacobi(args):
     print(json.dumps(out), flush=True)
 
 
+def run_reorder(args):
+    """RING <-> NESTED conversion of B maps at Nside (default 1024, B=16,
+    FP32): HBM-bound permutation, each pixel read and written once."""
+    import torch
+    import paper_2510_01785_amd as shtx
+    dev = torch.device("cuda:0")
+    nside, B = args.nside, args.batch
+    dt = {"f32": torch.float32, "f64": torch.float64, "bf16": torch.bfloat16}[args.dtype]
+    n = 12 * nside * nside
+    print("[bench] reorder nside=%d batch=%d %s" % (nside, B, args.dtype), flush=True)
+    x = torch.randn((B, n), device=dev, dtype=torch.float32).to(dt)
+    res = {}
+    for name, fn in (("nest2ring", shtx.nest2ring), ("ring2nest", shtx.ring2nest)):
+        for _ in range(args.warmup):
+            fn(x)
+        torch.cuda.synchronize()
+        evs = []
+        for _ in range(args.steps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn(x)
+            e1.record()
+            evs.append((e0, e1))
+        torch.cuda.synchronize()
+        ms = np.array([a.elapsed_time(b) for a, b in evs])
+        res[name] = float(np.median(ms))
+    nbytes = 2.0 * n * B * x.element_size()  # every pixel read once and written once
+    gbs = {k: nbytes / (v * 1e-3) / 1e9 for k, v in res.items()}
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import nested
+        m = x[0].float().cpu().numpy()
+        t0 = time.perf_counter()
+        reps = 0
+        while time.perf_counter() - t0 < 10.0:
+            nested.nest_to_ring(m, nside)
+            reps += 1
+        el = time.perf_counter() - t0
+        cpu = {"value": round(reps * n * 4 * 2 / el / 1e9, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
+               "sample": "nest_to_ring of one channel, %d repetitions in %.1f s" % (reps, el)}
+    worst = min(gbs.values())
+    out = {
+        "metric": "RING<->NESTED map reorder GB/s (read + write), Nside=%d B=%d" % (nside, B),
+        "value": round(worst, 1),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_call": {k: round(v, 4) for k, v in res.items()},
+        "gb_per_s": {k: round(v, 1) for k, v in gbs.items()},
+        "higher_is_better": True,
+        "dtype": args.dtype,
+        "data": "synthetic",
+        "roofline": {"kernel": "k_reorder", "bound": "hbm", "achieved": round(worst, 1), "peak": 8000.0,
+                     "unit": "GB/s", "frac": round(worst / 8000.0, 4), "traffic": None},
+        "cpu_baseline": cpu,
+        "config": {"workload": "healpix_reorder", "nside": nside, "batch": B},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -331,6 +393,8 @@ def main():
         return run_serving(args)
     if args.workload == "jacobi":
         return run_jacobi(args)
+    if args.workload == "reorder":
+        return run_reorder(args)
     import paper_2510_01785_amd as shtx
     from paper_2510_01785_amd import _lib, synth
 

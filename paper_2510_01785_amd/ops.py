@@ -208,3 +208,26 @@ def alm2map(alm, nside, lmax):
     x, squeeze = _as_batched(alm)
     out = Alm2Map.apply(x, nside, lmax)
     return out[0] if squeeze else out
+
+
+# ------------------------------------------------------- pixel order conversion
+def _reorder(fn, maps):
+    _check_device(maps)
+    x, squeeze = _as_batched(maps)
+    code = _DTYPES[x.dtype]
+    x = x.contiguous()
+    B, n = x.shape
+    nside = nside_of(n)
+    out = torch.empty_like(x)
+    _lib.check(fn, getattr(_lib.lib(), fn)(nside, B, code, x.data_ptr(), out.data_ptr(), _stream_ptr(x.device)))
+    return out[0] if squeeze else out
+
+
+def nest2ring(maps):
+    """NESTED-ordered maps [..., Npix] -> the same maps in RING order."""
+    return _reorder("shtx_nest2ring", maps)
+
+
+def ring2nest(maps):
+    """RING-ordered maps [..., Npix] -> the same maps in NESTED order."""
+    return _reorder("shtx_ring2nest", maps)

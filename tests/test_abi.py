@@ -105,3 +105,21 @@ def test_tables_build_validation():
     assert L.shtx_tables_build(8, 10, FAKE, 16, None) == _lib.ERR_WORKSPACE
     assert L.shtx_tables_build(4096, 10, FAKE, 1 << 40, None) == _lib.ERR_UNSUPPORTED
     assert L.shtx_tables_release(FAKE) == _lib.ERR_TABLES
+
+
+@pytest.mark.parametrize("fn", ["shtx_nest2ring", "shtx_ring2nest"])
+def test_reorder_validation_before_launch(fn):
+    L = _lib.lib()
+    f = getattr(L, fn)
+    big = 12 * 8 * 8 * 4 * 2  # bytes of one nside-8 FP32 map, twice
+    a, b = FAKE, FAKE + 4 * big
+    assert f(6, 1, 1, a, b, None) == _lib.ERR_ARG       # nside not a power of two
+    assert f(16384, 1, 1, a, b, None) == _lib.ERR_ARG   # nside above 8192
+    assert f(8, 0, 1, a, b, None) == _lib.ERR_ARG       # empty batch
+    assert f(8, 1, 7, a, b, None) == _lib.ERR_ARG       # unknown dtype
+    assert f(8, 1, 1, None, b, None) == _lib.ERR_ARG
+    assert f(8, 1, 1, a, None, None) == _lib.ERR_ARG
+    assert f(8, 1, 1, a + 2, b, None) == _lib.ERR_ARG   # FP32 element alignment
+    assert f(8, 1, 0, a, b + 4, None) == _lib.ERR_ARG   # FP64 element alignment
+    assert f(8, 1, 1, a, a + 64, None) == _lib.ERR_ARG  # overlapping input and output
+    assert f(8, 2, 1, a, a + 12 * 64 * 4, None) == _lib.ERR_ARG
