@@ -19,8 +19,9 @@
 // x + y = const is one contiguous run of one ring in RING order (slot j grows
 // by one as x - y grows by two; a run wraps at most once, at the ring's
 // start).  A workgroup moves one (square, channel) through LDS: the NESTED
-// side is copied as one contiguous block, the RING side one diagonal per
-// wave, lanes along the run, so both sides are read and written in runs.
+// side is copied as one contiguous block, the RING side by whole diagonals,
+// lanes along the runs (two diagonals per wave step where they fit), so both
+// sides are read and written in runs.
 #include <hip/hip_runtime.h>
 
 #include <stdint.h>
@@ -83,11 +84,31 @@ __global__ void __launch_bounds__(256) k_reorder(int lgn, int lgt, int B, int ve
       }
       __syncthreads();
     }
-    // diagonals d = x + y of the square, one per wave; lane k takes x = xmin + k
-    for (int d = w; d < 2 * T - 1; d += 4) {
+    // diagonals d = x + y of the square, lane k taking x = xmin(d) + k.  For
+    // T = 64 the diagonals go in pairs of 64 pixels in all (d, 62 - d) and
+    // (d, 190 - d), plus 31, 63 and 95 alone: 65 steps of one wave each;
+    // smaller squares take one diagonal per step.
+    const int nsteps = T == 64 ? 65 : 2 * T - 1;
+    for (int st = w; st < nsteps; st += 4) {
+      int da = st, db = -1;
+      if (T == 64) {
+        if (st < 31) {
+          db = 62 - st;
+        } else if (st == 32) {
+          da = 63;
+        } else if (st > 32 && st < 64) {
+          da = st + 31;
+          db = 159 - st;
+        } else if (st == 64) {
+          da = 95;
+        }
+      }
+      const int la = da < T ? da + 1 : 2 * T - 1 - da;
+      const int lb = db < 0 ? 0 : (db < T ? db + 1 : 2 * T - 1 - db);
+      if (lane >= la + lb) continue;
+      const int d = lane < la ? da : db;
+      const int k = lane < la ? lane : lane - la;
       const int xmin = d < T ? 0 : d - T + 1;
-      const int len = (d < T ? d : T - 1) - xmin + 1;
-      if (lane >= len) continue;
       const int i = rf * N - (X0 + Y0 + d) - 1;  // ring, 1 .. 4N-1
       int n, shift;
       uint32_t start;
@@ -104,8 +125,8 @@ __global__ void __launch_bounds__(256) k_reorder(int lgn, int lgt, int B, int ve
         shift = (i - N) & 1;
         start = 2u * (uint32_t)N * (uint32_t)(N - 1) + 4u * (uint32_t)N * (uint32_t)(i - N);
       }
-      const int x = xmin + lane, y = d - x;
-      int j = ((qf * n + (X0 + xmin) - (Y0 + d - xmin) + 1 + shift) >> 1) + lane;
+      const int x = xmin + k, y = d - x;
+      int j = ((qf * n + (X0 + xmin) - (Y0 + d - xmin) + 1 + shift) >> 1) + k;
       if (j > 4 * n) j -= 4 * n;
       if (j < 1) j += 4 * n;
       const size_t r = o + start + (uint32_t)(j - 1);
