@@ -16,6 +16,9 @@ the pins):
   sht.jacobi_map2alm          pinned (composition of pinned transforms; residual
                               decrease)
   sht.spectral_loss(_grad)    pinned (finite differences)
+  sht.resize_alm              pinned (zero extension leaves the synthesis
+                              unchanged, truncation commutes with the
+                              analysis, round trip)
   nested.*                    pinned (Nside-1 identity with the base-pixel
                               geometry, bijection, south/east/west/north
                               sub-pixels against the RING geometry)

@@ -214,3 +214,16 @@ def spectral_loss_grad(alm, lmax):
     """dL/d(alm) in the PyTorch complex convention: 2 w_l a_lm."""
     l = _l_of_index(lmax)
     return 2.0 * (1.0 / (l + 1.0))[None, :] * alm
+
+
+def resize_alm(alm, lmax_in, lmax_out):
+    """Coefficients of band limit lmax_in re-expressed at band limit lmax_out:
+    a_lm kept for l <= min(lmax_in, lmax_out), zero for lmax_in < l <= lmax_out
+    (truncation or zero extension of the spectrum; the map is unchanged by an
+    extension and band-limited by a truncation).  Plain loops."""
+    alm = np.asarray(alm)
+    out = np.zeros(alm.shape[:-1] + (geometry.nalm(lmax_out),), dtype=alm.dtype)
+    for m in range(min(lmax_in, lmax_out) + 1):
+        for l in range(m, min(lmax_in, lmax_out) + 1):
+            out[..., geometry.alm_index(l, m, lmax_out)] = alm[..., geometry.alm_index(l, m, lmax_in)]
+    return out
