@@ -41,11 +41,12 @@ def parse():
     ap.add_argument("--dtype", default="f32", choices=["f32", "f64", "bf16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-nside", type=int, default=None)
-    ap.add_argument("--workload", default="sht", choices=["sht", "serving", "jacobi", "reorder"],
+    ap.add_argument("--workload", default="sht", choices=["sht", "serving", "jacobi", "reorder", "resize"],
                     help="sht: forward+inverse throughput (default); serving: Poisson trace of mixed "
                          "requests through the serving loop vs one at a time; jacobi: 3-iteration "
                          "refined analysis at Nside=2048, lmax=4095, one map; reorder: RING <-> NESTED "
-                         "pixel order conversion of --batch maps at --nside")
+                         "pixel order conversion of --batch maps at --nside; resize: spectral resize of "
+                         "--batch coefficient sets from lmax 2 nside - 1 to 4 nside - 1")
     ap.add_argument("--requests", type=int, default=2000)
     ap.add_argument("--rate", type=float, default=200.0)
     ap.add_argument("--budget-gib", type=float, default=48.0)
@@ -371,6 +372,57 @@ def run_reorder(args):
     print(json.dumps(out), flush=True)
 
 
+def run_resize(args):
+    """Spectral resize of B coefficient sets from lmax = 2 nside - 1 to
+    4 nside - 1 (default 2047 -> 4095, B=16, FP32): HBM-bound copy with zero
+    fill, input read once and output written once."""
+    import torch
+    import paper_2510_01785_amd as shtx
+    from paper_2510_01785_amd import synth
+    dev = torch.device("cuda:0")
+    lin, lout, B = 2 * args.nside - 1, 4 * args.nside - 1, args.batch
+    ct = torch.complex128 if args.dtype == "f64" else torch.complex64
+    print("[bench] resize %d -> %d batch=%d %s" % (lin, lout, B, args.dtype), flush=True)
+    x = torch.tensor(synth.gaussian_alm(17853, B, lin, "lp10"), dtype=ct).to(dev)
+    res = {}
+    for name, (a, b, src) in (("extend", (lin, lout, x)), ("truncate", (lout, lin, None))):
+        if src is None:
+            src = shtx.alm_resize(x, lin, lout)
+        for _ in range(args.warmup):
+            shtx.alm_resize(src, a, b)
+        torch.cuda.synchronize()
+        evs = []
+        for _ in range(args.steps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            shtx.alm_resize(src, a, b)
+            e1.record()
+            evs.append((e0, e1))
+        torch.cuda.synchronize()
+        ms = float(np.median([u.elapsed_time(v) for u, v in evs]))
+        na, nb = (a + 1) * (a + 2) // 2, (b + 1) * (b + 2) // 2
+        nbytes = (min(na, nb) + nb) * B * x.element_size()  # kept coefficients read, output written
+        res[name] = (ms, nbytes / (ms * 1e-3) / 1e9)
+    worst = min(v[1] for v in res.values())
+    out = {
+        "metric": "spectral resize GB/s (read + write), lmax %d <-> %d, B=%d" % (lin, lout, B),
+        "value": round(worst, 1),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_call": {k: round(v[0], 4) for k, v in res.items()},
+        "gb_per_s": {k: round(v[1], 1) for k, v in res.items()},
+        "higher_is_better": True,
+        "dtype": args.dtype,
+        "data": "synthetic",
+        "roofline": {"kernel": "k_alm_resize", "bound": "hbm", "achieved": round(worst, 1), "peak": 8000.0,
+                     "unit": "GB/s", "frac": round(worst / 8000.0, 4), "traffic": None},
+        "config": {"workload": "healpix_alm_resize", "lmax_in": lin, "lmax_out": lout, "batch": B},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -395,6 +447,8 @@ def main():
         return run_jacobi(args)
     if args.workload == "reorder":
         return run_reorder(args)
+    if args.workload == "resize":
+        return run_resize(args)
     import paper_2510_01785_amd as shtx
     from paper_2510_01785_amd import _lib, synth
 

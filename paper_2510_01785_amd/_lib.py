@@ -12,7 +12,8 @@ EXPORTS = ("shtx_version", "shtx_status_string", "shtx_tables_bytes", "shtx_tabl
            "shtx_tables_release", "shtx_tables_work", "shtx_workspace_bytes", "shtx_map2alm", "shtx_alm2map",
            "shtx_map2alm_backward", "shtx_alm2map_backward", "shtx_iter_workspace_bytes",
            "shtx_map2alm_iter", "shtx_profile_enable",
-           "shtx_profile_reset", "shtx_profile_read", "shtx_stage_name", "shtx_nest2ring", "shtx_ring2nest")
+           "shtx_profile_reset", "shtx_profile_read", "shtx_stage_name", "shtx_nest2ring", "shtx_ring2nest",
+           "shtx_alm_resize")
 STAGES = ("ring_fft_fwd", "legendre_fwd", "alm_in", "legendre_inv", "ring_fft_inv")
 
 _lib = None
@@ -65,6 +66,8 @@ def lib():
     L.shtx_profile_read.restype = i
     L.shtx_stage_name.argtypes = [i]
     L.shtx_stage_name.restype = ctypes.c_char_p
+    L.shtx_alm_resize.argtypes = [i, i, i, i, vp, vp, vp]
+    L.shtx_alm_resize.restype = i
     for name in ("shtx_nest2ring", "shtx_ring2nest"):
         f = getattr(L, name)
         f.argtypes = [i, i, i, vp, vp, vp]

@@ -12,7 +12,7 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libshtx.so")
 SOURCES = ["api.hip", "tables.hip", "ring_fft.hip", "legendre_valu.hip", "legendre_mfma.hip", "layout.hip",
-           "reorder.hip"]
+           "reorder.hip", "resize.hip"]
 # Per-source flags.  The matrix-core kernels keep their accumulators in
 # ordinary VGPRs (gfx950's unified register file): with AGPR accumulators the
 # compiler copies them between the two register kinds around every

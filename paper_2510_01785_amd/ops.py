@@ -231,3 +231,19 @@ def nest2ring(maps):
 def ring2nest(maps):
     """RING-ordered maps [..., Npix] -> the same maps in NESTED order."""
     return _reorder("shtx_ring2nest", maps)
+
+
+# ------------------------------------------------------------ spectral resize
+def alm_resize(alm, lmax_in, lmax_out):
+    """alm [..., nalm(lmax_in)] complex -> [..., nalm(lmax_out)]: kept for
+    l <= min(lmax_in, lmax_out), zero above lmax_in."""
+    _check_device(alm)
+    x, squeeze = _as_batched(alm)
+    code = _ALM_CODE[x.dtype]
+    x = x.contiguous()
+    if x.shape[1] != nalm(lmax_in):
+        raise ValueError("alm has %d coefficients, not nalm(%d)" % (x.shape[1], lmax_in))
+    out = torch.empty((x.shape[0], nalm(lmax_out)), dtype=x.dtype, device=x.device)
+    _lib.check("shtx_alm_resize", _lib.lib().shtx_alm_resize(lmax_in, lmax_out, x.shape[0], code, x.data_ptr(),
+                                                             out.data_ptr(), _stream_ptr(x.device)))
+    return out[0] if squeeze else out

@@ -123,3 +123,18 @@ def test_reorder_validation_before_launch(fn):
     assert f(8, 1, 0, a, b + 4, None) == _lib.ERR_ARG   # FP64 element alignment
     assert f(8, 1, 1, a, a + 64, None) == _lib.ERR_ARG  # overlapping input and output
     assert f(8, 2, 1, a, a + 12 * 64 * 4, None) == _lib.ERR_ARG
+
+
+def test_alm_resize_validation_before_launch():
+    L = _lib.lib()
+    f = L.shtx_alm_resize
+    a, b = FAKE, FAKE + (1 << 30)
+    assert f(-1, 7, 1, 1, a, b, None) == _lib.ERR_ARG
+    assert f(7, 8192, 1, 1, a, b, None) == _lib.ERR_ARG
+    assert f(7, 9, 0, 1, a, b, None) == _lib.ERR_ARG
+    assert f(7, 9, 1, 2, a, b, None) == _lib.ERR_ARG      # BF16 coefficients do not exist
+    assert f(7, 9, 1, 1, None, b, None) == _lib.ERR_ARG
+    assert f(7, 9, 1, 1, a, None, None) == _lib.ERR_ARG
+    assert f(7, 9, 1, 1, a + 4, b, None) == _lib.ERR_ARG  # complex64 alignment
+    assert f(7, 9, 1, 0, a, b + 8, None) == _lib.ERR_ARG  # complex128 alignment
+    assert f(7, 9, 1, 1, a, a + 8, None) == _lib.ERR_ARG  # overlap
