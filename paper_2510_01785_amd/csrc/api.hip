@@ -360,6 +360,27 @@ int shtx_map2alm(int nside, int lmax, int batch, int dtype, const void *map, voi
   }
 }
 
+int shtx_map2alm_weighted(int nside, int lmax, int batch, int dtype, const void *map, void *alm,
+                          const double *ring_weights, const void *tables, void *work, size_t work_bytes,
+                          void *stream) {
+  if (!ring_weights || (reinterpret_cast<uintptr_t>(ring_weights) & 7)) return SHTX_ERR_ARG;
+  Tables tb;
+  int s = check_common(nside, lmax, batch, dtype, map, alm, tables, work, work_bytes, &tb, true);
+  if (s != SHTX_OK) return s;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  switch (dtype) {
+    case SHTX_F64:
+      return run_analysis<double, double>(tb, batch, static_cast<const double *>(map), static_cast<double2 *>(alm),
+                                          ring_weights, 1.0, 1.0, 1.0, work, st);
+    case SHTX_F32:
+      return run_analysis<float, float>(tb, batch, static_cast<const float *>(map), static_cast<float2 *>(alm),
+                                        ring_weights, 1.0, 1.0, 1.0, work, st);
+    default:
+      return run_analysis<bf16_t, float>(tb, batch, static_cast<const bf16_t *>(map), static_cast<float2 *>(alm),
+                                         ring_weights, 1.0, 1.0, 1.0, work, st);
+  }
+}
+
 int shtx_alm2map(int nside, int lmax, int batch, int dtype, const void *alm, void *map, const void *tables,
                  void *work, size_t work_bytes, void *stream) {
   Tables tb;

@@ -247,3 +247,27 @@ def alm_resize(alm, lmax_in, lmax_out):
     _lib.check("shtx_alm_resize", _lib.lib().shtx_alm_resize(lmax_in, lmax_out, x.shape[0], code, x.data_ptr(),
                                                              out.data_ptr(), _stream_ptr(x.device)))
     return out[0] if squeeze else out
+
+
+# ------------------------------------------------------- ring-weighted analysis
+def map2alm_weighted_raw(maps, lmax, ring_weights):
+    """Analysis with per-ring quadrature weights: maps [B, Npix] (RING),
+    ring_weights [2 nside] float64 on the maps' device (entry p: north ring
+    p + 1 and its southern mirror) -> alm [B, nalm].  No autograd."""
+    _check_device(maps)
+    code = _DTYPES[maps.dtype]
+    maps = maps.contiguous()
+    B, n = maps.shape
+    nside = nside_of(n)
+    w = ring_weights.to(device=maps.device, dtype=torch.float64).contiguous()
+    if w.numel() != 2 * nside:
+        raise ValueError("ring_weights needs 2*nside = %d entries" % (2 * nside))
+    out = torch.empty((B, nalm(lmax)), dtype=_ALM_DTYPE[code], device=maps.device)
+    L = _lib.lib()
+    tab = get_tables(nside, lmax, maps.device)
+    wb = L.shtx_workspace_bytes(nside, lmax, B, code)
+    work = torch.empty(wb, dtype=torch.uint8, device=maps.device)
+    _lib.check("shtx_map2alm_weighted",
+               L.shtx_map2alm_weighted(nside, lmax, B, code, maps.data_ptr(), out.data_ptr(), w.data_ptr(),
+                                       tab.data_ptr(), work.data_ptr(), wb, _stream_ptr(maps.device)))
+    return out

@@ -138,3 +138,13 @@ def test_alm_resize_validation_before_launch():
     assert f(7, 9, 1, 1, a + 4, b, None) == _lib.ERR_ARG  # complex64 alignment
     assert f(7, 9, 1, 0, a, b + 8, None) == _lib.ERR_ARG  # complex128 alignment
     assert f(7, 9, 1, 1, a, a + 8, None) == _lib.ERR_ARG  # overlap
+
+
+def test_weighted_analysis_validation_before_launch():
+    L = _lib.lib()
+    f = L.shtx_map2alm_weighted
+    wb = L.shtx_workspace_bytes(8, 15, 2, 1)
+    assert f(8, 15, 2, 1, FAKE, FAKE, None, FAKE, FAKE, wb, None) == _lib.ERR_ARG      # no weights
+    assert f(8, 15, 2, 1, FAKE, FAKE, FAKE + 4, FAKE, FAKE, wb, None) == _lib.ERR_ARG  # misaligned weights
+    assert f(6, 15, 2, 1, FAKE, FAKE, FAKE, FAKE, FAKE, wb, None) == _lib.ERR_ARG
+    assert f(8, 15, 2, 1, FAKE, FAKE, FAKE, FAKE, FAKE, wb, None) == _lib.ERR_TABLES   # tables never built
