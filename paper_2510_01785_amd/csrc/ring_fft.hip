@@ -676,6 +676,25 @@ template <> __device__ __forceinline__ void load4<float, bf16_t>(const bf16_t *p
   v[3] = __uint_as_float(q.y & 0xffff0000u);
 }
 
+// Four consecutive map pixels (the caller guarantees 4-element alignment, as
+// for load4): one 16-byte store (FP32), two (FP64) or one 8-byte store of
+// four rounded bfloat16 values.
+template <typename S, typename T> __device__ __forceinline__ void store4(S *p, const T (&v)[4]);
+template <> __device__ __forceinline__ void store4<float, float>(float *p, const float (&v)[4]) {
+  *reinterpret_cast<float4 *>(p) = make_float4(v[0], v[1], v[2], v[3]);
+}
+template <> __device__ __forceinline__ void store4<double, double>(double *p, const double (&v)[4]) {
+  reinterpret_cast<double2 *>(p)[0] = make_double2(v[0], v[1]);
+  reinterpret_cast<double2 *>(p)[1] = make_double2(v[2], v[3]);
+}
+template <> __device__ __forceinline__ void store4<bf16_t, float>(bf16_t *p, const float (&v)[4]) {
+  bf16_t t[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) store_as<bf16_t, float>(&t[e], v[e]);
+  *reinterpret_cast<uint2 *>(p) = make_uint2((uint32_t)t[0].bits | ((uint32_t)t[1].bits << 16),
+                                             (uint32_t)t[2].bits | ((uint32_t)t[3].bits << 16));
+}
+
 // Two adjacent complex values (FP32: one 16-byte store).
 __device__ __forceinline__ void store_pair(float2 *p, float2 a, float2 b) {
   *reinterpret_cast<float4 *>(p) = make_float4(a.x, a.y, b.x, b.y);
@@ -920,23 +939,34 @@ __global__ void __launch_bounds__(NT, sizeof(T) == 4 ? 4 : 1)
       __syncthreads();
       ring_dft<T, NT>(tb, buf, tq, n, gc, pad, b0 != bg0);
     }
-    if (sub) {
-      // residual sub - S a of an iterative refinement (TOut = T)
-      for (int j = tid; j < gc * n; j += NT) {
-        const int c = j / n, jj = j - c * n;
-        const C F = buf[lidx(j, pad)];
-        const size_t r = (size_t)(b0 + c) * npix;
-        store_as<TOut, T>(map + r + sN + jj, load_as<T, TOut>(sub + r + sN + jj) - F.x);
-        if (!equator) store_as<TOut, T>(map + r + sS + jj, load_as<T, TOut>(sub + r + sS + jj) + F.y);
+    // IDFT(h) = conj(F): f_N = F.x, f_S = -F.y; four consecutive pixels per
+    // item (ring starts and lengths are multiples of 4 pixels)
+    const int nq = n >> 2;
+    for (int q = tid; q < gc * nq; q += NT) {
+      const int c = q / nq, jj = 4 * (q - c * nq);
+      const int j = c * n + jj;
+      T fn[4], fs[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const C F = buf[lidx(j + e, pad)];
+        fn[e] = F.x;
+        fs[e] = -F.y;
       }
-    } else {
-      for (int j = tid; j < gc * n; j += NT) {
-        const int c = j / n, jj = j - c * n;
-        const C F = buf[lidx(j, pad)];  // IDFT(h) = conj(F): f_N = F.x, f_S = -F.y
-        TOut *row = map + (size_t)(b0 + c) * npix;
-        store_as<TOut, T>(row + sN + jj, F.x);
-        if (!equator) store_as<TOut, T>(row + sS + jj, -F.y);
+      const size_t r = (size_t)(b0 + c) * npix;
+      if (sub) {
+        // residual sub - S a of an iterative refinement (TOut = T)
+        T sv[4];
+        load4<T, TOut>(sub + r + sN + jj, sv);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) fn[e] = sv[e] - fn[e];
+        if (!equator) {
+          load4<T, TOut>(sub + r + sS + jj, sv);
+#pragma unroll
+          for (int e = 0; e < 4; ++e) fs[e] = sv[e] - fs[e];
+        }
       }
+      store4<TOut, T>(map + r + sN + jj, fn);
+      if (!equator) store4<TOut, T>(map + r + sS + jj, fs);
     }
     __syncthreads();
   }
