@@ -37,8 +37,9 @@ static_assert(kFwdWaves * kBlockL * kRedRS <= kFwdWaves * kSubL * kTileRS, "redu
 // even or odd l) with the ring spectra E or O held in registers.  The four
 // waves' partial sums are added through LDS at the end.
 __global__ void __launch_bounds__(256)
-    k_legendre_fwd_mfma(Tables tb, int B, int b0, const double *__restrict__ coefA, const float2 *__restrict__ XE,
+    k_legendre_fwd_mfma(Tables tb, int B, const double *__restrict__ coefA, const float2 *__restrict__ XE,
                         const float2 *__restrict__ XO, float2 *__restrict__ alm, float f0, float fm, int accum) {
+  const int b0 = 16 * blockIdx.y;  // channel group of this row of the grid
   __shared__ float tile[kFwdWaves * kSubL * kTileRS];
   __shared__ double sA[kBlockL];
   const int g = blockIdx.x;
@@ -274,8 +275,9 @@ __device__ __forceinline__ void pair_halves(float x, float y, float &lo, float &
 }
 
 __global__ void __launch_bounds__(64)
-    k_legendre_inv_mfma(Tables tb, int B, int b0, const double *__restrict__ coefA, const float2 *__restrict__ ALMT,
+    k_legendre_inv_mfma(Tables tb, int B, const double *__restrict__ coefA, const float2 *__restrict__ ALMT,
                         SynLayout lay, float2 *__restrict__ GN, float2 *__restrict__ GS) {
+  const int b0 = 16 * blockIdx.y;  // channel group of this row of the grid
   const int L = tb.lmax, M = L + 1, Rp = tb.npairs;
   const int nch = (Rp + kInvRings - 1) / kInvRings;
   const int g = blockIdx.x;
@@ -458,9 +460,9 @@ hipError_t launch_legendre_fwd_mfma(const Tables &tb, int B, const float2 *XE, c
       longest = c > longest ? c : longest;
     }
   }
-  for (int b0 = 0; b0 < B; b0 += 16)
-    hipLaunchKernelGGL(k_legendre_fwd_mfma, dim3(8 * longest), dim3(256), 0, st, tb, B, b0, tb.coefA, XE, XO,
-                       alm, (float)f0, (float)fm, accum);
+  // all 16-channel groups in one launch (one tail instead of one per group)
+  hipLaunchKernelGGL(k_legendre_fwd_mfma, dim3(8 * longest, (B + 15) / 16), dim3(256), 0, st, tb, B, tb.coefA, XE,
+                     XO, alm, (float)f0, (float)fm, accum);
   return hipGetLastError();
 }
 
@@ -469,9 +471,8 @@ hipError_t launch_legendre_inv_mfma(const Tables &tb, int B, const float2 *ALMT,
   const int nch = (tb.npairs + kInvRings - 1) / kInvRings;
   const int noct = (tb.lmax + 1 + 7) / 8;
   const int per_xcd = ((noct + 7) / 8) * 8 * nch;  // octets per XCD x 8 m x chunks
-  for (int b0 = 0; b0 < B; b0 += 16)
-    hipLaunchKernelGGL(k_legendre_inv_mfma, dim3(8 * per_xcd), dim3(64), 0, st, tb, B, b0, tb.coefA, ALMT, lay,
-                       GN, GS);
+  hipLaunchKernelGGL(k_legendre_inv_mfma, dim3(8 * per_xcd, (B + 15) / 16), dim3(64), 0, st, tb, B, tb.coefA,
+                     ALMT, lay, GN, GS);
   return hipGetLastError();
 }
 
