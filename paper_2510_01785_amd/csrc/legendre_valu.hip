@@ -40,8 +40,9 @@ template <typename T, int BG> struct FwdValuShape {
 template <typename T, int BG, int R>
 __global__ void __launch_bounds__(256)
     __attribute__((amdgpu_waves_per_eu(FwdValuShape<T, BG>::kWaves, FwdValuShape<T, BG>::kWaves)))
-    k_legendre_fwd_valu(Tables tb, int B, int b0, const cplx<T> *__restrict__ XE, const cplx<T> *__restrict__ XO,
+    k_legendre_fwd_valu(Tables tb, int B, int bbase, const cplx<T> *__restrict__ XE, const cplx<T> *__restrict__ XO,
                         cplx<T> *__restrict__ alm, T f0, T fm, int accum) {
+  const int b0 = bbase + BG * (int)blockIdx.y;  // channel group of this row of the grid
   using C = cplx<T>;
   constexpr int NW = 4;
   constexpr int SLOTS = FwdValuShape<T, BG>::kSlots, RS = FwdValuShape<T, BG>::kRS;
@@ -231,8 +232,9 @@ __device__ __forceinline__ float keep_if(float v, bool keep) {
 // XCD.
 template <typename T, int BG, int R>
 __global__ void __launch_bounds__(64)
-    k_legendre_inv_valu(Tables tb, int B, int b0, const cplx<T> *__restrict__ ALMT, SynLayout lay,
+    k_legendre_inv_valu(Tables tb, int B, int bbase, const cplx<T> *__restrict__ ALMT, SynLayout lay,
                         cplx<T> *__restrict__ GN, cplx<T> *__restrict__ GS) {
+  const int b0 = bbase + BG * (int)blockIdx.y;  // channel group of this row of the grid
   using C = cplx<T>;
   typedef __attribute__((address_space(4))) const double cdouble;
   typedef __attribute__((address_space(4))) const T creal;
@@ -350,16 +352,16 @@ __global__ void __launch_bounds__(64)
 }
 
 template <typename T, int BG, int R>
-static void launch_fwd_cfg(const Tables &tb, int B, int b0, const cplx<T> *XE, const cplx<T> *XO, cplx<T> *alm,
-                           double f0, double fm, int accum, hipStream_t st) {
+static void launch_fwd_cfg(const Tables &tb, int B, int b0, int ngroups, const cplx<T> *XE, const cplx<T> *XO,
+                           cplx<T> *alm, double f0, double fm, int accum, hipStream_t st) {
   int longest = 0;  // items of the largest XCD group (m = x mod 8, blocks of kBlockL l's)
   for (int x = 0; x < 8; ++x) {
     int c = 0;
     for (int m = x; m <= tb.lmax; m += 8) c += (tb.lmax - m + kBlockL) / kBlockL;
     longest = std::max(longest, c);
   }
-  hipLaunchKernelGGL((k_legendre_fwd_valu<T, BG, R>), dim3(8 * longest), dim3(256), 0, st, tb, B, b0, XE, XO, alm,
-                     (T)f0, (T)fm, accum);
+  hipLaunchKernelGGL((k_legendre_fwd_valu<T, BG, R>), dim3(8 * longest, ngroups), dim3(256), 0, st, tb, B, b0, XE,
+                     XO, alm, (T)f0, (T)fm, accum);
 }
 
 // Channel groups of 2 (FP64) or 4 (FP32), then 2 and 1 for the rest; writes
@@ -369,23 +371,26 @@ template <typename T>
 hipError_t launch_legendre_fwd_valu(const Tables &tb, int B, const cplx<T> *XE, const cplx<T> *XO, cplx<T> *alm,
                                     double f0, double fm, int accum, hipStream_t st) {
   if (tb.nitems == 0) return hipErrorInvalidValue;
+  // the groups of one width in one launch (one tail per width)
   int b0 = 0;
   if constexpr (sizeof(T) == 4) {
-    for (; b0 + 4 <= B; b0 += 4) launch_fwd_cfg<T, 4, 2>(tb, B, b0, XE, XO, alm, f0, fm, accum, st);
+    if (B >= 4) launch_fwd_cfg<T, 4, 2>(tb, B, b0, B / 4, XE, XO, alm, f0, fm, accum, st);
+    b0 = B / 4 * 4;
   }
-  for (; b0 + 2 <= B; b0 += 2) launch_fwd_cfg<T, 2, 2>(tb, B, b0, XE, XO, alm, f0, fm, accum, st);
-  if (b0 < B) launch_fwd_cfg<T, 1, 4>(tb, B, b0, XE, XO, alm, f0, fm, accum, st);
+  if (B - b0 >= 2) launch_fwd_cfg<T, 2, 2>(tb, B, b0, (B - b0) / 2, XE, XO, alm, f0, fm, accum, st);
+  b0 += (B - b0) / 2 * 2;
+  if (b0 < B) launch_fwd_cfg<T, 1, 4>(tb, B, b0, 1, XE, XO, alm, f0, fm, accum, st);
   return hipGetLastError();
 }
 
 template <typename T, int BG>
-static void launch_inv_cfg(const Tables &tb, int B, int b0, const cplx<T> *ALMT, SynLayout lay, cplx<T> *GN,
-                           cplx<T> *GS, hipStream_t st) {
+static void launch_inv_cfg(const Tables &tb, int B, int b0, int ngroups, const cplx<T> *ALMT, SynLayout lay,
+                           cplx<T> *GN, cplx<T> *GS, hipStream_t st) {
   constexpr int R = BG == 1 ? 4 : 2;  // ring pairs per lane
   const int nch = (tb.npairs + 64 * R - 1) / (64 * R);
   const int nm = (tb.lmax + 1 + 7) / 8;
-  hipLaunchKernelGGL((k_legendre_inv_valu<T, BG, R>), dim3(8 * nm * nch), dim3(64), 0, st, tb, B, b0, ALMT, lay,
-                     GN, GS);
+  hipLaunchKernelGGL((k_legendre_inv_valu<T, BG, R>), dim3(8 * nm * nch, ngroups), dim3(64), 0, st, tb, B, b0,
+                     ALMT, lay, GN, GS);
 }
 
 // Channel groups of 4 (FP32) or 2 (FP64), then 2 and 1 for the rest: the
@@ -395,12 +400,13 @@ hipError_t launch_legendre_inv_valu(const Tables &tb, int B, const cplx<T> *ALMT
                                     cplx<T> *GS, hipStream_t st) {
   constexpr int BGMAX = sizeof(T) == 8 ? 2 : 4;
   int b0 = 0;
-  for (; b0 + BGMAX <= B; b0 += BGMAX) launch_inv_cfg<T, BGMAX>(tb, B, b0, ALMT, lay, GN, GS, st);
+  if (B >= BGMAX) launch_inv_cfg<T, BGMAX>(tb, B, 0, B / BGMAX, ALMT, lay, GN, GS, st);  // one launch per width
+  b0 = B / BGMAX * BGMAX;
   if (BGMAX == 4 && b0 + 2 <= B) {
-    launch_inv_cfg<T, 2>(tb, B, b0, ALMT, lay, GN, GS, st);
+    launch_inv_cfg<T, 2>(tb, B, b0, 1, ALMT, lay, GN, GS, st);
     b0 += 2;
   }
-  if (b0 < B) launch_inv_cfg<T, 1>(tb, B, b0, ALMT, lay, GN, GS, st);
+  if (b0 < B) launch_inv_cfg<T, 1>(tb, B, b0, 1, ALMT, lay, GN, GS, st);
   return hipGetLastError();
 }
 
