@@ -158,8 +158,8 @@ def map2alm_backward(grad_alm, nside, lmax, nthreads=None):
     """Gradient w.r.t. the map of a real loss, given dL/d(alm).
 
     Complex gradients follow PyTorch (dL/dRe + i dL/dIm).  With equal
-    weights w = 4 pi/Npix the adjoint of map2alm (the adjoint SHT "W Y",
-    Sec. III-F) on the m >= 0 storage is w * alm2map(G') with
+    weights w = 4 pi/Npix the adjoint of map2alm (Sec. III-F: the synthesis
+    scaled by the quadrature weights) on the m >= 0 storage is w * alm2map(G') with
     G'_l0 = Re G_l0 and G'_lm = G_lm / 2 for m > 0.
     """
     G = np.atleast_2d(np.asarray(grad_alm, dtype=np.complex128)).copy()
@@ -172,7 +172,8 @@ def map2alm_backward(grad_alm, nside, lmax, nthreads=None):
 def alm2map_backward(grad_map, lmax, nside=None, nthreads=None):
     """Gradient w.r.t. alm of a real loss, given dL/d(map).
 
-    The adjoint iSHT "Y^dagger" (Sec. III-F) on the m >= 0 storage is the
+    The adjoint of the synthesis (Sec. III-F: the conjugate transpose of its
+    matrix) on the m >= 0 storage is the
     unit-weight analysis sum, doubled for m > 0 (each stored a_lm also stands
     for a_{l,-m}); the m = 0 gradient is real.
     """
