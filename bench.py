@@ -27,6 +27,7 @@ PEAK = {  # MI355X published peaks
     "fp32_vector_TFs": 157.3,
     "fp64_vector_TFs": 78.6,
     "fp32_mfma_TFs": 157.3,
+    "bf16_mfma_TFs": 2500.0,
 }
 
 
@@ -40,7 +41,6 @@ def parse():
     ap.add_argument("--batch", type=int, default=16)
     ap.add_argument("--dtype", default="f32", choices=["f32", "f64", "bf16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-nside", type=int, default=None)
     ap.add_argument("--workload", default="sht", choices=["sht", "serving", "jacobi", "reorder", "resize"],
                     help="sht: forward+inverse throughput (default); serving: Poisson trace of mixed "
                          "requests through the serving loop vs one at a time; jacobi: 3-iteration "
@@ -104,22 +104,73 @@ def measured_traffic(kernel, fname, workload):
     return float(m.group(2)) + float(m.group(3))
 
 
-def cpu_baseline(nside, lmax, seed):
-    """The FP64 oracle, as it stands, on one map of the same workload: forward
-    + inverse, all host threads."""
-    from oracle import _clib, sht
+def rel_l2(got, ref):
+    return float(np.linalg.norm((got - ref).ravel()) / max(np.linalg.norm(ref.ravel()), 1e-300))
+
+
+def per_l_max_rel(got, ref, lmax):
+    """max over l of |a_l. - ref_l.| / |ref_l.| (norms over m = 0..l), and its l."""
     from paper_2510_01785_amd import synth
-    alm = synth.gaussian_alm(seed, 1, lmax, "lp10")
-    f = synth.white_map(seed, 1, 12 * nside * nside)
+    ls, _ = synth.lm_arrays(lmax)
+    num = np.bincount(ls, weights=np.abs(got - ref) ** 2, minlength=lmax + 1)
+    den = np.bincount(ls, weights=np.abs(ref) ** 2, minlength=lmax + 1)
+    r = np.sqrt(num / np.maximum(den, 1e-300))
+    return float(r.max()), int(r.argmax())
+
+
+def oracle_check(nside, lmax, f0, a0_gpu, g0_gpu):
+    """The FP64 oracle, as it stands, on channel 0 of the timed step: its
+    forward transform of the timed input map f0 and its inverse transform of
+    the step's own coefficients a0_gpu.  Timed (forward + inverse, all host
+    threads) as the CPU baseline, and compared element by element with the
+    step's outputs (a0_gpu, and g0_gpu = the step's synthesis of a0_gpu, or
+    None for a forward-only step): relative l2 and the largest per-l relative
+    error of the coefficients, relative l2 of the map, and the round-trip
+    error f0 - S(A(f0)) of the GPU path (RMS and max, relative to f0)."""
+    from oracle import _clib, sht
     _clib.build()
     t0 = time.perf_counter()
-    a = sht.map2alm(f, lmax, nside)
-    sht.alm2map(alm, nside, lmax)
+    a_ref = sht.map2alm(f0[None, :], lmax, nside)[0]
+    g_ref = sht.alm2map(a0_gpu[None, :].astype(np.complex128), nside, lmax)[0]
     dt = time.perf_counter() - t0
-    del a
-    return dict(value=1.0 / dt, unit="maps/s", cores=_clib.threads(), kind="oracle",
-                sample="1 channel of the workload (nside=%d, lmax=%d), forward + inverse, %.1f s"
-                % (nside, lmax, dt))
+    acc = {"map2alm_rel_l2": float("%.3e" % rel_l2(a0_gpu, a_ref))}
+    worst, lw = per_l_max_rel(a0_gpu, a_ref, lmax)
+    acc["map2alm_per_l_max_rel"] = float("%.3e" % worst)
+    acc["map2alm_per_l_max_at_l"] = lw
+    if g0_gpu is not None:
+        acc["alm2map_rel_l2"] = float("%.3e" % rel_l2(g0_gpu, g_ref))
+        d = f0 - g0_gpu
+        acc["round_trip_rms_rel"] = float("%.3e" % (np.sqrt(np.mean(d ** 2)) / np.sqrt(np.mean(f0 ** 2))))
+        acc["round_trip_max_rel"] = float("%.3e" % (np.abs(d).max() / np.abs(f0).max()))
+    acc["oracle"] = "FP64 CPU oracle on channel 0 of the timed step"
+    cpu = dict(value=round(1.0 / dt, 5), unit="maps/s", cores=_clib.threads(), kind="oracle",
+               sample="channel 0 of the timed step (nside=%d, lmax=%d): oracle forward of its input map "
+                      "+ inverse of its coefficients, %.1f s" % (nside, lmax, dt))
+    return acc, cpu
+
+
+def stage_peak(bound, dtype):
+    if bound == "hbm":
+        return PEAK["hbm_GBs"] * 1e9
+    if bound == "mfma":
+        return PEAK["bf16_mfma_TFs" if dtype == "bf16" else "fp32_mfma_TFs"] * 1e12
+    return (PEAK["fp64_vector_TFs"] if dtype == "f64" else PEAK["fp32_vector_TFs"]) * 1e12
+
+
+def step_roofline(stages, work, dtype, B, ms_per_step):
+    """Roofline time of the whole step: per stage the algorithmic work over
+    the peak of its bound (HBM bytes, or contraction flops on the executed
+    triangle), summed over the stages the step runs, against the measured
+    step time."""
+    per = {}
+    for k, v in stages.items():
+        bound, amount, _ = work[k]
+        if k.startswith("legendre"):
+            bound = "mfma" if on_mfma(k, dtype, B) else "alu"
+        per[k] = amount / stage_peak(bound, dtype) * 1e3 * v["calls_per_step"]
+    t = sum(per.values())
+    return {"t_roof_ms": round(t, 4), "t_measured_ms": round(ms_per_step, 4), "frac": round(t / ms_per_step, 4),
+            "stages_roof_ms": {k: round(v, 4) for k, v in per.items()}}
 
 
 def run_serving(args):
@@ -495,18 +546,19 @@ def main():
     prof = _lib.profile_read()
     lat = np.array([a.elapsed_time(b) for a, b in evs])
     print("[bench] timed %d steps in %.3f s" % (args.steps, wall), flush=True)
-    # accuracy of one analysis of the synthesised maps against the coefficients
-    # they were made from (quadrature error of Eq. (1) plus rounding)
-    a_chk = shtx.map2alm_raw(maps, lmax).to(alm0.dtype)
-    diff = (a_chk - alm0).abs()
-    roundtrip = {"rel_l2": float("%.3e" % (torch.linalg.vector_norm(a_chk - alm0) / torch.linalg.vector_norm(alm0)).item()),
-                 "rel_linf": float("%.3e" % (diff.max() / alm0.abs().max()).item())}
-    del a_chk, diff
+    # the step's outputs for channel 0 (the transforms are deterministic: the
+    # same values as every timed step), kept for the oracle comparison
+    a_step = shtx.map2alm_raw(maps, lmax)
+    f0 = maps[0].double().cpu().numpy()
+    a0_gpu = a_step[0].cpu().numpy()
+    g0_gpu = None if args.dtype == "bf16" else shtx.alm2map_raw(a_step, nside, lmax)[0].double().cpu().numpy()
+    del a_step
 
     value = B * args.steps / wall
     ms_per_step = 1000.0 * wall / args.steps
     # roofline of the dominant stage
-    stages = {k: dict(ms_per_call=v[0] / max(v[1], 1), calls=v[1]) for k, v in prof.items() if v[1]}
+    stages = {k: dict(ms_per_call=v[0] / max(v[1], 1), calls=v[1], calls_per_step=v[1] / args.steps)
+              for k, v in prof.items() if v[1]}
     dom = max(stages, key=lambda k: stages[k]["ms_per_call"])
     csize = 16 if args.dtype == "f64" else 8
     esize = {"f32": 4, "f64": 8, "bf16": 2}[args.dtype]
@@ -568,12 +620,11 @@ def main():
                    "fields": "gaussian C_l=(l+10)^-2"},
         "stages_ms_per_call": {k: round(v["ms_per_call"], 4) for k, v in stages.items()},
         "roofline": roof,
-        "analysis_vs_input_alm": roundtrip,
+        "step_roofline": step_roofline(stages, work, args.dtype, B, ms_per_step),
     }
     if not args.no_cpu_baseline:
-        print("[bench] cpu baseline (oracle)", flush=True)
-        cs = args.cpu_sample_nside or nside
-        out["cpu_baseline"] = cpu_baseline(cs, 2 * cs - 1, seed)
+        print("[bench] oracle on channel 0 of the timed step (accuracy + cpu baseline)", flush=True)
+        out["accuracy_vs_oracle"], out["cpu_baseline"] = oracle_check(nside, lmax, f0, a0_gpu, g0_gpu)
     print(json.dumps(out), flush=True)
 
 

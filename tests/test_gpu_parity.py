@@ -60,6 +60,13 @@ CASES = [
     # nside 256 FP32, 2 + 1 at nside 512 FP64)
     (256, 300, 11, torch.float32),
     (512, 600, 3, torch.float64),
+    # FP64 with several channel groups of the vector-ALU kernels on the grid's
+    # second dimension (groups of 2: 8 groups, and 2 + 2 + 1)
+    (64, 191, 16, torch.float64),
+    (32, 95, 5, torch.float64),
+    # batched FP32 transforms at nside 256, lmax 767, 64 channels: four
+    # 16-channel groups of the matrix-core kernels in one launch at lmax = 3N-1
+    (256, 767, 64, torch.float32),
 ]
 
 
@@ -91,6 +98,7 @@ def test_alm2map_parity(shtx, nside, lmax, batch, dtype):
 
 
 @pytest.mark.parametrize("nside,lmax,batch,dtype", [(4, 15, 2, torch.float64), (16, 47, 2, torch.float64),
+                                                    (16, 47, 6, torch.float64),
                                                     (8, 23, 3, torch.float32), (16, 47, 9, torch.float32),
                                                     (32, 95, 18, torch.float32)])
 def test_backward_parity(shtx, nside, lmax, batch, dtype):
@@ -146,6 +154,7 @@ _PATH_ENV = {"mfma": ("0", "1"), "valu": ("1", "1"), "default": ("0", None)}
 
 @pytest.mark.parametrize("nside,lmax,batch,path", [(32, 95, 16, "mfma"), (64, 255, 20, "mfma"), (16, 47, 3, "mfma"),
                                                    (32, 95, 7, "valu"), (64, 191, 1, "valu"), (32, 95, 6, "valu"),
+                                                   (32, 95, 13, "valu"),
                                                    (64, 191, 3, "default"), (64, 191, 6, "default"),
                                                    (64, 191, 9, "default")])
 def test_fp32_legendre_paths(shtx, nside, lmax, batch, path, monkeypatch):
@@ -166,6 +175,39 @@ def test_fp32_legendre_paths(shtx, nside, lmax, batch, path, monkeypatch):
     g = shtx.alm2map(a, nside, lmax).cpu().numpy()
     gref = sht.alm2map(a.cpu().numpy().astype(np.complex128), nside, lmax)
     assert rel_l2(g, gref) <= 1e-5
+
+
+# BF16 gradient maps are the FP32 result rounded to nearest even: each value
+# carries a relative rounding error of at most 2^-9, so the relative l2 error
+# against the FP64 oracle is at most 2^-9 plus the FP32 arithmetic (~1e-7).
+BF16_ROUND_TOL = 2.0 ** -9 + 1e-5
+
+
+@pytest.mark.parametrize("batch", [2, 9])
+def test_bf16_map_autograd(shtx, batch):
+    """Map2Alm on bfloat16 maps at nside 16, lmax 47: the backward writes a
+    bfloat16 gradient map (the adjoint of Sec. III-F), compared with the
+    oracle's map2alm_backward of the same upstream gradient; B=2 takes the
+    vector-ALU synthesis kernel, B=9 the matrix-core one."""
+    nside, lmax = 16, 47
+    announce("bf16 autograd nside=%d lmax=%d B=%d" % (nside, lmax, batch))
+    f = band_limited_map(6100 + batch, batch, nside, lmax) + synth.white_map(6100 + batch, batch, 12 * nside * nside)
+    x = torch.tensor(f, dtype=torch.float32, device="cuda").to(torch.bfloat16).requires_grad_(True)
+    a = shtx.map2alm(x, lmax)
+    assert a.dtype == torch.complex64
+    ls, _ = synth.lm_arrays(lmax)
+    w = torch.tensor(1.0 / (ls + 1.0), device="cuda", dtype=torch.float32)
+    loss = (w * a.abs() ** 2).sum()
+    loss.backward()
+    g = x.grad
+    assert g.dtype == torch.bfloat16 and g.shape == x.shape
+    a_ref = sht.map2alm(x.detach().float().double().cpu().numpy(), lmax, nside)
+    ref = sht.map2alm_backward(sht.spectral_loss_grad(a_ref, lmax), nside, lmax)
+    err = rel_l2(g.float().double().cpu().numpy(), ref)
+    print("[bf16 autograd] B=%d rel l2 of the bf16 gradient map vs oracle %.3e" % (batch, err), flush=True)
+    assert err <= BF16_ROUND_TOL
+    # the map2alm of the same bf16 maps is FP32-accurate (the input is exact)
+    assert rel_l2(a.detach().cpu().numpy(), a_ref) <= 1e-5
 
 
 def test_deterministic(shtx):

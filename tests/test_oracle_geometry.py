@@ -1,6 +1,7 @@
 """Pins for the oracle's HEALPix RING geometry (oracle/geometry.py)."""
 import json
 import os
+from fractions import Fraction
 
 import numpy as np
 import pytest
@@ -29,6 +30,39 @@ def test_base_resolution_pixel_centres(golden_dir):
     theta, phi = geometry.pixel_angles(ref["nside"])
     np.testing.assert_allclose(np.cos(theta), ref["z"], atol=1e-15)
     np.testing.assert_allclose(phi / np.pi, ref["phi_over_pi"], atol=1e-15)
+
+
+def _frac(s):
+    return float(Fraction(s))
+
+
+def test_pixel_centres_nside2(golden_dir):
+    """Every pixel centre at nside 2 against the hand-written fixture: the
+    polar-cap rings carry the cap offset pi/(4i), the belt rings alternate
+    pi/(4N) and 0 (Sec. III-A and the grid definition it cites)."""
+    with open(os.path.join(golden_dir, "healpix_pixel_centres_nside2_4.json")) as f:
+        ref = json.load(f)["nside2_pixels"]
+    theta, phi = geometry.pixel_angles(2)
+    np.testing.assert_allclose(np.cos(theta), [_frac(v) for v in ref["z"]], atol=2e-16)
+    np.testing.assert_allclose(np.asarray(phi) / np.pi, [_frac(v) for v in ref["phi_over_pi"]], atol=1e-15)
+
+
+def test_ring_first_centres_nside4(golden_dir):
+    """nside 4: length, z and first-pixel longitude of every ring (three cap
+    rings on each side), and the even spacing within each ring."""
+    with open(os.path.join(golden_dir, "healpix_pixel_centres_nside2_4.json")) as f:
+        rings = json.load(f)["nside4_rings"]
+    g = geometry.ring_geometry(4)
+    theta, phi = geometry.pixel_angles(4)
+    assert len(rings) == len(g["n"])
+    for rr in rings:
+        r = rr["i"] - 1
+        s, n = int(g["start"][r]), int(g["n"][r])
+        assert n == rr["n"]
+        assert abs(g["z"][r] - _frac(rr["z"])) <= 2e-16
+        want = _frac(rr["phi_first_over_pi"]) + 2.0 * np.arange(n) / n
+        np.testing.assert_allclose(np.asarray(phi[s:s + n]) / np.pi, want, atol=1e-15)
+        np.testing.assert_allclose(np.cos(theta[s:s + n]), _frac(rr["z"]), atol=2e-16)
 
 
 @pytest.mark.parametrize("nside", [1, 2, 4, 8, 64, 1024])

@@ -69,6 +69,21 @@ def test_children_are_south_east_west_north(nside):
 
 
 @pytest.mark.parametrize("nside", [1, 2, 4, 8, 16])
+def test_east_west_children_symmetric_about_parent(nside):
+    # the east and west parts of a pixel lie on one ring at longitudes
+    # symmetric about the parent's centre, to rounding (this also fixes the
+    # longitude offsets of the cap rings relative to each other)
+    _, _, phi1 = unit_vectors(nside)
+    _, _, phi2 = unit_vectors(2 * nside)
+    parents = np.arange(12 * nside * nside)
+    pphi = phi1[nested.nest_to_ring_index(nside, parents)]
+    pe = phi2[nested.nest_to_ring_index(2 * nside, 4 * parents + 1)]
+    pw = phi2[nested.nest_to_ring_index(2 * nside, 4 * parents + 2)]
+    off = np.angle(np.exp(1j * (pe - pphi))) + np.angle(np.exp(1j * (pw - pphi)))
+    assert np.max(np.abs(off)) <= 1e-14
+
+
+@pytest.mark.parametrize("nside", [1, 2, 4, 8, 16])
 def test_children_surround_their_parent(nside):
     # the four parts of a pixel lie within about one parent pixel of its centre
     vp, _, _ = unit_vectors(nside)

@@ -149,3 +149,14 @@ def test_gpu_mix_equals_alone():
     for a, o in zip(alone, outs):
         assert torch.equal(a, o)
     assert st["requests"] == 12 and st["peak_in_use_bytes"] <= 2 << 30
+    # and each served result is the transform: FP32 parity with the FP64 oracle
+    from oracle import sht
+    for (d, nside, lmax, x), o in zip(reqs, outs):
+        xin = x.cpu().numpy()
+        if d == "map2alm":
+            ref = sht.map2alm(xin.astype(np.float64), lmax, nside)
+        else:
+            ref = sht.alm2map(xin.astype(np.complex128), nside, lmax)
+        got = o.cpu().numpy()
+        err = np.linalg.norm((got - ref).ravel()) / np.linalg.norm(ref.ravel())
+        assert err <= 1e-5, (d, nside, lmax, err)
