@@ -71,8 +71,15 @@ def on_mfma(stage, dtype, batch):
     return dtype in ("f32", "bf16") and batch >= MFMA_MIN_BATCH[d]
 
 
+def bf16_mfma(stage, dtype, batch):
+    """BF16 maps take the BF16 matrix-core analysis from the FP32 switch point."""
+    return stage == "legendre_fwd" and dtype == "bf16" and batch >= MFMA_MIN_BATCH["fwd"]
+
+
 def stage_kernel(stage, dtype, batch):
     """(kernel symbol, source file) that runs `stage`."""
+    if bf16_mfma(stage, dtype, batch):
+        return ("k_legendre_fwd_bf16", "legendre_bf16.hip")
     if stage.startswith("legendre"):
         d = stage.split("_")[1]
         return ("k_legendre_%s_mfma" % d, "legendre_mfma.hip") if on_mfma(stage, dtype, batch) else \
@@ -150,10 +157,13 @@ def oracle_check(nside, lmax, f0, a0_gpu, g0_gpu):
 
 
 def stage_peak(bound, dtype):
+    """Peak (flop/s or B/s) of a stage's bound: FP32 matrix cores for FP32
+    contraction (BF16 maps on the FP32 contraction too), the vector ALUs of
+    the compute precision otherwise."""
     if bound == "hbm":
         return PEAK["hbm_GBs"] * 1e9
     if bound == "mfma":
-        return PEAK["bf16_mfma_TFs" if dtype == "bf16" else "fp32_mfma_TFs"] * 1e12
+        return PEAK["fp32_mfma_TFs"] * 1e12
     return (PEAK["fp64_vector_TFs"] if dtype == "f64" else PEAK["fp32_vector_TFs"]) * 1e12
 
 
@@ -164,10 +174,8 @@ def step_roofline(stages, work, dtype, B, ms_per_step):
     step time."""
     per = {}
     for k, v in stages.items():
-        bound, amount, _ = work[k]
-        if k.startswith("legendre"):
-            bound = "mfma" if on_mfma(k, dtype, B) else "alu"
-        per[k] = amount / stage_peak(bound, dtype) * 1e3 * v["calls_per_step"]
+        _, amount, unit, peak = work[k]
+        per[k] = amount / (peak * (1e12 if unit == "TFLOP/s" else 1e9)) * 1e3 * v["calls_per_step"]
     t = sum(per.values())
     return {"t_roof_ms": round(t, 4), "t_measured_ms": round(ms_per_step, 4), "frac": round(t / ms_per_step, 4),
             "stages_roof_ms": {k: round(v, 4) for k, v in per.items()}}
@@ -566,32 +574,37 @@ def main():
     spec_bytes = 2 * (lmax + 1) * 2 * nside * B * csize
     alm_bytes = (lmax + 1) * (lmax + 2) // 2 * B * csize
     mfma = dom.startswith("legendre") and on_mfma(dom, args.dtype, B)
-    leg_bound = "mfma" if mfma else "alu"
     # Legendre work: 4 flops (complex += real * complex) per executed (l, m,
     # ring pair) triple and channel; the executed triangle skips the l where
     # lambda_lm(z_p) is negligible (the full triangle is reported beside it)
+    bf_ = "mfma" if on_mfma("legendre_fwd", args.dtype, B) else "alu"
+    bi_ = "mfma" if on_mfma("legendre_inv", args.dtype, B) else "alu"
+    # BF16 spectra: 4 bytes per complex value
+    spec_fwd = spec_bytes // 2 if bf16_mfma("legendre_fwd", args.dtype, B) else spec_bytes
     work = {
-        # algorithmic work per call of each stage
-        "legendre_fwd": (leg_bound, 4.0 * executed * B, "TFLOP/s"),
-        "legendre_inv": (leg_bound, 4.0 * executed * B, "TFLOP/s"),
-        "ring_fft_fwd": ("hbm", float(npix * B * esize + spec_bytes), "GB/s"),
-        "ring_fft_inv": ("hbm", float(npix * B * esize + spec_bytes), "GB/s"),
-        "alm_in": ("hbm", 2.0 * alm_bytes, "GB/s"),
+        # algorithmic work per call of each stage: (bound, amount, unit, peak)
+        "legendre_fwd": (bf_, 4.0 * executed * B, "TFLOP/s", stage_peak(bf_, args.dtype) / 1e12),
+        "legendre_inv": (bi_, 4.0 * executed * B, "TFLOP/s", stage_peak(bi_, args.dtype) / 1e12),
+        "ring_fft_fwd": ("hbm", float(npix * B * esize + spec_fwd), "GB/s", PEAK["hbm_GBs"]),
+        "ring_fft_inv": ("hbm", float(npix * B * esize + spec_bytes), "GB/s", PEAK["hbm_GBs"]),
+        "alm_in": ("hbm", 2.0 * alm_bytes, "GB/s", PEAK["hbm_GBs"]),
     }
-    bound, amount, unit = work[dom]
+    if bf16_mfma("legendre_fwd", args.dtype, B):
+        # BF16 matrix-core analysis: the BF16 contraction (4 T_exec B flops)
+        # takes 4 T_exec B / 2.5 PFLOP/s, below the FP64 recurrence it is fed
+        # by (a multiply and a fused multiply-add, 3 flops, per executed
+        # triple, shared by the channels) at the FP64 vector peak: that binds
+        t_mfma = 4.0 * executed * B / (PEAK["bf16_mfma_TFs"] * 1e12)
+        t_rec = 3.0 * executed / (PEAK["fp64_vector_TFs"] * 1e12)
+        work["legendre_fwd"] = (("alu", 3.0 * executed, "TFLOP/s", PEAK["fp64_vector_TFs"]) if t_rec >= t_mfma else
+                                ("mfma", 4.0 * executed * B, "TFLOP/s", PEAK["bf16_mfma_TFs"]))
+    bound, amount, unit, peak = work[dom]
     sec = stages[dom]["ms_per_call"] / 1000.0
-    if unit == "TFLOP/s":
-        achieved = amount / sec / 1e12
-        if bound == "mfma":
-            peak = PEAK["fp32_mfma_TFs"]
-        else:
-            peak = PEAK["fp64_vector_TFs"] if args.dtype == "f64" else PEAK["fp32_vector_TFs"]
-    else:
-        achieved = amount / sec / 1e9
-        peak = PEAK["hbm_GBs"]
+    achieved = amount / sec / (1e12 if unit == "TFLOP/s" else 1e9)
     workload = "nside%d_lmax%d_b%d_%s" % (nside, lmax, B, args.dtype)
     kname, kfile = stage_kernel(dom, args.dtype, B)
-    traffic = measured_traffic(kname, kfile, workload) if (mfma or unit != "TFLOP/s") else None
+    traffic = measured_traffic(kname, kfile, workload) if (mfma or unit != "TFLOP/s" or
+                                                          bf16_mfma(dom, args.dtype, B)) else None
     roof = dict(kernel=kname, bound=bound, achieved=round(achieved, 3), peak=peak, unit=unit,
                 frac=round(achieved / peak, 4), traffic=traffic,
                 algorithmic=amount, per="launch" if B <= 16 else "call")

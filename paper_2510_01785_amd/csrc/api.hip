@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <cstdlib>
 #include <mutex>
+#include <type_traits>
 #include <unordered_map>
 #include <utility>
 #include <vector>
@@ -13,9 +14,10 @@
 namespace shtx {
 
 hipError_t launch_tables_build(int nside, int lmax, void *base, hipStream_t st);
-template <typename TIn, typename T>
-hipError_t launch_ring_fft_fwd(Tables, int, const TIn *, const double *, double, cplx<T> *, cplx<T> *,
-                               hipStream_t);
+template <typename TIn, typename T, typename TS>
+hipError_t launch_ring_fft_fwd(Tables, int, const TIn *, const double *, double, TS *, TS *, hipStream_t);
+hipError_t launch_legendre_fwd_bf16(const Tables &, int, const uint32_t *, const uint32_t *, float2 *, double, double,
+                                    int, hipStream_t);
 template <typename TOut, typename T>
 hipError_t launch_ring_fft_inv(Tables, int, const cplx<T> *, const cplx<T> *, const TOut *, TOut *, hipStream_t);
 template <typename T>
@@ -148,6 +150,48 @@ template <typename T> Work<T> carve(void *work, const Tables &tb, int batch) {
 
 constexpr int kMaxIter = 64;  // refinement iterations accepted by shtx_map2alm_iter
 
+// ---------------------------------------------- allocation-free analysis
+// Fixed device scratch of shtx_map2alm_noalloc: the two analysis spectrum
+// buffers live here instead of in a caller workspace.  One copy per device,
+// held until the process ends; calls on one device share it.
+constexpr size_t kScratchBytes = (size_t)SHTX_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};  // device address of `scratch` per device
+
+// Device address of this device's scratch array (looked up once per device,
+// with that device current); nullptr on failure.
+void *scratch_ptr(int *status) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+    *status = SHTX_ERR_HIP;
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+      *status = SHTX_ERR_HIP;
+      return nullptr;
+    }
+    g_scratch_ptr[dev] = p;
+  }
+  *status = SHTX_OK;
+  return g_scratch_ptr[dev];
+}
+
+// Scratch bytes an analysis needs: the two spectrum buffers (the coefficient
+// buffer of the workspace serves only the synthesis).
+size_t analysis_scratch_bytes(int nside, int lmax, int batch, int dtype) {
+  const size_t cs = dtype == SHTX_F64 ? 16 : 8;
+  size_t nbhat;
+  int mmax_bs;
+  bluestein_sizes(nside, &nbhat, &mmax_bs);
+  return 2 * align_up(spec_bytes(nside, lmax, mmax_bs, batch, cs), 256);
+}
+
 int status_of(hipError_t e) { return e == hipSuccess ? SHTX_OK : SHTX_ERR_HIP; }
 
 // Matrix-core Legendre kernels serve FP32 contraction from mfma_min_batch()
@@ -195,15 +239,41 @@ template <> hipError_t legendre_inv<float>(const Tables &tb, int B, const float2
   return launch_legendre_inv_valu<float>(tb, B, ALMT, lay, GN, GS, st);
 }
 
+// BF16 maps take the BF16 matrix-core contraction (BF16 spectra and
+// Legendre operands, FP32 accumulation) where the FP32 analysis would take
+// the matrix cores; SHTX_BF16_CONTRACT=f32 in the environment (read per
+// call) keeps them on the FP32 contraction.
+template <typename TIn> bool bf16_contraction(const Tables &tb, int B) {
+  if constexpr (!std::is_same<TIn, bf16_t>::value) {
+    return false;
+  } else {
+    const char *e = getenv("SHTX_BF16_CONTRACT");
+    if (e && e[0] == 'f') return false;
+    return B >= mfma_min_batch(false) && mfma_fwd_supported(tb) && !force_valu();
+  }
+}
+
 // analysis chain: ring FFT -> Legendre -> caller layout with factors
 template <typename TIn, typename T>
 int run_analysis(const Tables &tb, int B, const TIn *map, cplx<T> *alm, const double *wtab, double wscale,
                  double f0, double fm, void *work, hipStream_t st, int accumulate = 0) {
   Work<T> w = carve<T>(work, tb, B);
   hipError_t e;
+  if constexpr (std::is_same<T, float>::value) {
+    if (bf16_contraction<TIn>(tb, B)) {
+      uint32_t *sa = reinterpret_cast<uint32_t *>(w.specA), *sb = reinterpret_cast<uint32_t *>(w.specB);
+      {
+        StageTimer t(kStFftFwd, st);
+        e = launch_ring_fft_fwd<TIn, T, uint32_t>(tb, B, map, wtab, wscale, sa, sb, st);
+      }
+      if (e != hipSuccess) return SHTX_ERR_HIP;
+      StageTimer t(kStLegFwd, st);
+      return status_of(launch_legendre_fwd_bf16(tb, B, sa, sb, alm, f0, fm, accumulate, st));
+    }
+  }
   {
     StageTimer t(kStFftFwd, st);
-    e = launch_ring_fft_fwd<TIn, T>(tb, B, map, wtab, wscale, w.specA, w.specB, st);
+    e = launch_ring_fft_fwd<TIn, T, cplx<T>>(tb, B, map, wtab, wscale, w.specA, w.specB, st);
   }
   if (e != hipSuccess) return SHTX_ERR_HIP;
   StageTimer t(kStLegFwd, st);
@@ -280,6 +350,7 @@ const char *shtx_status_string(int status) {
     case SHTX_ERR_WORKSPACE: return "workspace too small";
     case SHTX_ERR_HIP: return "HIP runtime error";
     case SHTX_ERR_TABLES: return "tables not built for this (nside, lmax)";
+    case SHTX_ERR_SCRATCH: return "request needs more than the fixed scratch of the allocation-free entry point";
     default: return "unknown status";
   }
 }
@@ -345,6 +416,37 @@ int shtx_map2alm(int nside, int lmax, int batch, int dtype, const void *map, voi
                  void *work, size_t work_bytes, void *stream) {
   Tables tb;
   int s = check_common(nside, lmax, batch, dtype, map, alm, tables, work, work_bytes, &tb, true);
+  if (s != SHTX_OK) return s;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  switch (dtype) {
+    case SHTX_F64:
+      return run_analysis<double, double>(tb, batch, static_cast<const double *>(map), static_cast<double2 *>(alm),
+                                          tb.rp_w, 1.0, 1.0, 1.0, work, st);
+    case SHTX_F32:
+      return run_analysis<float, float>(tb, batch, static_cast<const float *>(map), static_cast<float2 *>(alm),
+                                        tb.rp_w, 1.0, 1.0, 1.0, work, st);
+    default:
+      return run_analysis<bf16_t, float>(tb, batch, static_cast<const bf16_t *>(map), static_cast<float2 *>(alm),
+                                         tb.rp_w, 1.0, 1.0, 1.0, work, st);
+  }
+}
+
+size_t shtx_noalloc_scratch_bytes(void) { return kScratchBytes; }
+
+int shtx_map2alm_noalloc(int nside, int lmax, int batch, int dtype, const void *map, void *alm, const void *tables,
+                         void *stream) {
+  if (!valid_geom(nside, lmax) || batch < 1) return SHTX_ERR_ARG;
+  if (dtype != SHTX_F64 && dtype != SHTX_F32 && dtype != SHTX_BF16) return SHTX_ERR_ARG;
+  if (nside > kMaxNside) return SHTX_ERR_UNSUPPORTED;
+  const size_t need = analysis_scratch_bytes(nside, lmax, batch, dtype);
+  if (need > kScratchBytes) return SHTX_ERR_SCRATCH;
+  int s = SHTX_OK;
+  void *work = scratch_ptr(&s);
+  if (!work) return s;
+  Tables tb;
+  // the scratch stands in for a workspace of exactly the analysis' size
+  s = check_common(nside, lmax, batch, dtype, map, alm, tables, work, shtx_workspace_bytes(nside, lmax, batch, dtype),
+                   &tb, true);
   if (s != SHTX_OK) return s;
   hipStream_t st = static_cast<hipStream_t>(stream);
   switch (dtype) {

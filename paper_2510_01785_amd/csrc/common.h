@@ -344,4 +344,13 @@ template <> __device__ __forceinline__ void store_as<bf16_t, float>(bf16_t *p, f
   p->bits = (uint16_t)(u >> 16);
 }
 
+// Two floats rounded to BF16 (nearest even) in one 32-bit word, `lo` in bits
+// 0-15: a complex value (re, im) of the BF16 ring spectra, or two Legendre
+// values of the BF16 matrix-core operands.
+__device__ __forceinline__ uint32_t pack_bf16x2(float lo, float hi) {
+  typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+  const bf16x2_t v = {(__bf16)lo, (__bf16)hi};
+  return __builtin_bit_cast(uint32_t, v);
+}
+
 }  // namespace shtx

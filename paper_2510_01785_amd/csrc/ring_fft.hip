@@ -695,7 +695,13 @@ template <> __device__ __forceinline__ void store4<bf16_t, float>(bf16_t *p, con
                                              (uint32_t)t[2].bits | ((uint32_t)t[3].bits << 16));
 }
 
-// Two adjacent complex values (FP32: one 16-byte store).
+// Analysis spectra are stored as the compute type's complex, or as BF16
+// complex words (re in bits 0-15) for the BF16 matrix-core Legendre step.
+__device__ __forceinline__ void store_spec(float2 *p, float2 v) { *p = v; }
+__device__ __forceinline__ void store_spec(double2 *p, double2 v) { *p = v; }
+__device__ __forceinline__ void store_spec(uint32_t *p, float2 v) { *p = pack_bf16x2(v.x, v.y); }
+
+// Two adjacent complex values (FP32: one 16-byte store; BF16: one 8-byte store).
 __device__ __forceinline__ void store_pair(float2 *p, float2 a, float2 b) {
   *reinterpret_cast<float4 *>(p) = make_float4(a.x, a.y, b.x, b.y);
 }
@@ -703,14 +709,16 @@ __device__ __forceinline__ void store_pair(double2 *p, double2 a, double2 b) {
   p[0] = a;
   p[1] = b;
 }
+__device__ __forceinline__ void store_pair(uint32_t *p, float2 a, float2 b) {
+  *reinterpret_cast<uint2 *>(p) = make_uint2(pack_bf16x2(a.x, a.y), pack_bf16x2(b.x, b.y));
+}
 
 constexpr int kLoadUnroll = 2;  // quads of pixels in flight per thread
 
-template <typename TIn, typename T, int NT>
+template <typename TIn, typename T, typename TS, int NT>
 __global__ void __launch_bounds__(NT, sizeof(T) == 4 ? 4 : 1)
     k_ring_fft_fwd(Tables tb, int B, int G, int tq_off, int bs_nb, const TIn *__restrict__ map,
-                   const double *__restrict__ wtab, double wscale, cplx<T> *__restrict__ XE,
-                   cplx<T> *__restrict__ XO) {
+                   const double *__restrict__ wtab, double wscale, TS *__restrict__ XE, TS *__restrict__ XO) {
   using C = cplx<T>;
   extern __shared__ unsigned char smem_raw[];
   C *buf = reinterpret_cast<C *>(smem_raw);
@@ -783,8 +791,8 @@ __global__ void __launch_bounds__(NT, sizeof(T) == 4 ? 4 : 1)
       C ph = rph.minus(mm);
       ph.x *= w;
       ph.y *= w;
-      C *xe = XE + obase + (size_t)m * B;
-      C *xo = XO + obase + (size_t)m * B;
+      TS *xe = XE + obase + (size_t)m * B;
+      TS *xo = XO + obase + (size_t)m * B;
       int c = 0;
       // U = DFT(fN+fS)[k] = (G[k] + conj(G[-k]))/2 ; V = DFT(fN-fS)[k] = (G[k] - conj(G[-k]))/(2i)
       auto uv = [&](int cc, C &U, C &V) {
@@ -805,8 +813,8 @@ __global__ void __launch_bounds__(NT, sizeof(T) == 4 ? 4 : 1)
       for (; c < gc; ++c) {
         C U, V;
         uv(c, U, V);
-        xe[c] = U;
-        xo[c] = V;
+        store_spec(xe + c, U);
+        store_spec(xo + c, V);
       }
     }
     __syncthreads();
@@ -1023,12 +1031,12 @@ template <typename K> hipError_t allow_lds(K kern, size_t lds) {
   return hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
-template <typename TIn, typename T>
-hipError_t launch_ring_fft_fwd(Tables tb, int B, const TIn *map, const double *wtab, double wscale, cplx<T> *XE,
-                               cplx<T> *XO, hipStream_t st) {
+template <typename TIn, typename T, typename TS>
+hipError_t launch_ring_fft_fwd(Tables tb, int B, const TIn *map, const double *wtab, double wscale, TS *XE, TS *XO,
+                               hipStream_t st) {
   const FftGeom g = fft_geometry(tb.nside, tb.mmax_bs, B, sizeof(cplx<T>));
   if (g.lds > kMaxLds) return hipErrorInvalidValue;
-  auto kern = k_ring_fft_fwd<TIn, T, kFftThreads>;
+  auto kern = k_ring_fft_fwd<TIn, T, TS, kFftThreads>;
   hipError_t e = allow_lds(kern, g.lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(kern, dim3(fft_grid(tb.npairs, B, g.G)), dim3(kFftThreads), g.lds, st, tb, B, g.G, g.tq_off,
@@ -1049,12 +1057,14 @@ hipError_t launch_ring_fft_inv(Tables tb, int B, const cplx<T> *GN, const cplx<T
   return hipGetLastError();
 }
 
-template hipError_t launch_ring_fft_fwd<double, double>(Tables, int, const double *, const double *, double,
-                                                        double2 *, double2 *, hipStream_t);
-template hipError_t launch_ring_fft_fwd<float, float>(Tables, int, const float *, const double *, double, float2 *,
-                                                      float2 *, hipStream_t);
-template hipError_t launch_ring_fft_fwd<bf16_t, float>(Tables, int, const bf16_t *, const double *, double,
-                                                       float2 *, float2 *, hipStream_t);
+template hipError_t launch_ring_fft_fwd<double, double, double2>(Tables, int, const double *, const double *, double,
+                                                                 double2 *, double2 *, hipStream_t);
+template hipError_t launch_ring_fft_fwd<float, float, float2>(Tables, int, const float *, const double *, double,
+                                                              float2 *, float2 *, hipStream_t);
+template hipError_t launch_ring_fft_fwd<bf16_t, float, float2>(Tables, int, const bf16_t *, const double *, double,
+                                                               float2 *, float2 *, hipStream_t);
+template hipError_t launch_ring_fft_fwd<bf16_t, float, uint32_t>(Tables, int, const bf16_t *, const double *,
+                                                                 double, uint32_t *, uint32_t *, hipStream_t);
 template hipError_t launch_ring_fft_inv<double, double>(Tables, int, const double2 *, const double2 *,
                                                         const double *, double *, hipStream_t);
 template hipError_t launch_ring_fft_inv<float, float>(Tables, int, const float2 *, const float2 *, const float *,

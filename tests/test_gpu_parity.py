@@ -181,6 +181,13 @@ def test_fp32_legendre_paths(shtx, nside, lmax, batch, path, monkeypatch):
 # carries a relative rounding error of at most 2^-9, so the relative l2 error
 # against the FP64 oracle is at most 2^-9 plus the FP32 arithmetic (~1e-7).
 BF16_ROUND_TOL = 2.0 ** -9 + 1e-5
+# BF16 matrix-core analysis (BF16 maps, from 5 channels): every product
+# lambda * X has both factors rounded to BF16 (relative 2^-9 each), so each
+# term carries at most 2^-8 relative error; for sums of white-noise terms
+# without strong cancellation the relative l2 error of a_lm is of that order.
+# The bar is 2^-8 times a cancellation allowance of 2.5 (a wrong operand
+# layout or a lost term gives O(1) errors); the measured value is printed.
+BF16_CONTRACT_TOL = 2.5 * 2.0 ** -8
 
 
 @pytest.mark.parametrize("batch", [2, 9])
@@ -201,13 +208,42 @@ def test_bf16_map_autograd(shtx, batch):
     loss.backward()
     g = x.grad
     assert g.dtype == torch.bfloat16 and g.shape == x.shape
+    a_gpu = a.detach().cpu().numpy().astype(np.complex128)
     a_ref = sht.map2alm(x.detach().float().double().cpu().numpy(), lmax, nside)
-    ref = sht.map2alm_backward(sht.spectral_loss_grad(a_ref, lmax), nside, lmax)
+    # the backward (the adjoint of Sec. III-F) applied to the upstream
+    # gradient of the forward's own output, by the oracle
+    ref = sht.map2alm_backward(sht.spectral_loss_grad(a_gpu, lmax), nside, lmax)
     err = rel_l2(g.float().double().cpu().numpy(), ref)
-    print("[bf16 autograd] B=%d rel l2 of the bf16 gradient map vs oracle %.3e" % (batch, err), flush=True)
+    ea = rel_l2(a_gpu, a_ref)
+    print("[bf16 autograd] B=%d rel l2: bf16 gradient map %.3e, forward a_lm %.3e" % (batch, err, ea), flush=True)
     assert err <= BF16_ROUND_TOL
-    # the map2alm of the same bf16 maps is FP32-accurate (the input is exact)
-    assert rel_l2(a.detach().cpu().numpy(), a_ref) <= 1e-5
+    # the forward: FP32 contraction below 5 channels, BF16 from 5
+    assert ea <= (1e-5 if batch < 5 else BF16_CONTRACT_TOL)
+
+
+@pytest.mark.parametrize("nside,lmax,batch", [(16, 47, 5), (32, 95, 16), (64, 191, 20), (64, 255, 13),
+                                              (128, 383, 16), (256, 767, 64), (32, 127, 6), (8, 31, 7)])
+def test_bf16_contraction_parity(shtx, nside, lmax, batch, monkeypatch):
+    """BF16 maps through the BF16 matrix-core analysis (BF16 spectra and
+    Legendre operands, FP32 accumulation) against the FP64 oracle on the same
+    BF16-rounded maps; and the same maps with SHTX_BF16_CONTRACT=f32 (FP32
+    contraction) at the FP32 tolerance.  Batches not a multiple of 4 take the
+    per-channel spectrum loads, B = 20 a partial 16-channel group."""
+    announce("bf16 contraction nside=%d lmax=%d B=%d" % (nside, lmax, batch))
+    f = synth.white_map(6200 + batch, batch, geometry.npix(nside))
+    x = torch.tensor(f, dtype=torch.float32, device="cuda").to(torch.bfloat16)
+    ref = sht.map2alm(x.float().double().cpu().numpy(), lmax, nside)
+    monkeypatch.delenv("SHTX_BF16_CONTRACT", raising=False)
+    monkeypatch.delenv("SHTX_FORCE_VALU", raising=False)
+    monkeypatch.delenv("SHTX_MFMA_MIN_BATCH", raising=False)
+    got = shtx.map2alm(x, lmax).cpu().numpy()
+    err = rel_l2(got, ref)
+    print("[bf16 contraction] nside=%d lmax=%d B=%d rel l2 vs oracle %.3e" % (nside, lmax, batch, err), flush=True)
+    assert np.all(got[:, :lmax + 1].imag == 0)
+    assert err <= BF16_CONTRACT_TOL
+    monkeypatch.setenv("SHTX_BF16_CONTRACT", "f32")
+    got32 = shtx.map2alm(x, lmax).cpu().numpy()
+    assert rel_l2(got32, ref) <= 1e-5
 
 
 def test_deterministic(shtx):
