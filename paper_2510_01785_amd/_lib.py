@@ -6,14 +6,14 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libshtx.so")
 
 F64, F32, BF16 = 0, 1, 2
-OK, ERR_ARG, ERR_UNSUPPORTED, ERR_WORKSPACE, ERR_HIP, ERR_TABLES, ERR_SCRATCH = range(7)
+OK, ERR_ARG, ERR_UNSUPPORTED, ERR_WORKSPACE, ERR_HIP, ERR_TABLES = range(6)
 
 EXPORTS = ("shtx_version", "shtx_status_string", "shtx_tables_bytes", "shtx_tables_build",
            "shtx_tables_release", "shtx_tables_work", "shtx_workspace_bytes", "shtx_map2alm", "shtx_alm2map",
            "shtx_map2alm_backward", "shtx_alm2map_backward", "shtx_iter_workspace_bytes",
            "shtx_map2alm_iter", "shtx_profile_enable",
            "shtx_profile_reset", "shtx_profile_read", "shtx_stage_name", "shtx_nest2ring", "shtx_ring2nest",
-           "shtx_alm_resize", "shtx_map2alm_weighted", "shtx_noalloc_scratch_bytes", "shtx_map2alm_noalloc")
+           "shtx_alm_resize", "shtx_map2alm_weighted")
 STAGES = ("ring_fft_fwd", "legendre_fwd", "alm_in", "legendre_inv", "ring_fft_inv")
 
 _lib = None
@@ -68,10 +68,6 @@ def lib():
     L.shtx_stage_name.restype = ctypes.c_char_p
     L.shtx_map2alm_weighted.argtypes = [i, i, i, i, vp, vp, vp, vp, vp, sz, vp]
     L.shtx_map2alm_weighted.restype = i
-    L.shtx_noalloc_scratch_bytes.argtypes = []
-    L.shtx_noalloc_scratch_bytes.restype = sz
-    L.shtx_map2alm_noalloc.argtypes = [i, i, i, i, vp, vp, vp, vp]
-    L.shtx_map2alm_noalloc.restype = i
     L.shtx_alm_resize.argtypes = [i, i, i, i, vp, vp, vp]
     L.shtx_alm_resize.restype = i
     for name in ("shtx_nest2ring", "shtx_ring2nest"):
