@@ -41,12 +41,14 @@ def parse():
     ap.add_argument("--batch", type=int, default=16)
     ap.add_argument("--dtype", default="f32", choices=["f32", "f64", "bf16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="sht", choices=["sht", "serving", "jacobi", "reorder", "resize"],
+    ap.add_argument("--workload", default="sht", choices=["sht", "serving", "jacobi", "reorder", "resize", "grad", "nested"],
                     help="sht: forward+inverse throughput (default); serving: Poisson trace of mixed "
                          "requests through the serving loop vs one at a time; jacobi: 3-iteration "
                          "refined analysis at Nside=2048, lmax=4095, one map; reorder: RING <-> NESTED "
                          "pixel order conversion of --batch maps at --nside; resize: spectral resize of "
-                         "--batch coefficient sets from lmax 2 nside - 1 to 4 nside - 1")
+                         "--batch coefficient sets from lmax 2 nside - 1 to 4 nside - 1; grad: forward + "
+                         "spectral loss + adjoint backward at --nside, --batch, --dtype; nested: analysis of "
+                         "NESTED maps, fused layout conversion vs nest2ring + map2alm")
     ap.add_argument("--requests", type=int, default=2000)
     ap.add_argument("--rate", type=float, default=200.0)
     ap.add_argument("--budget-gib", type=float, default=48.0)
@@ -276,6 +278,94 @@ def run_serving(args):
     print(json.dumps(out), flush=True)
 
 
+def run_grad(args):
+    """Differentiable workload: forward map2alm of B maps at Nside (default
+    1024, lmax 2047, B 16), the spectral loss sum_l w_l sum_m |a_lm|^2 with
+    w_l = 1/(l+1), and its backward through the hand-written adjoint chain
+    (torch.autograd.Function) to the gradient map; FP32 or BF16 maps.  One
+    step = forward + loss + backward; the loss's elementwise terms run as torch
+    operations on the coefficients (0.27 GB at the default size)."""
+    import torch
+    import paper_2510_01785_amd as shtx
+    from paper_2510_01785_amd import _lib, synth
+    dev = torch.device("cuda:0")
+    nside, B = args.nside, args.batch
+    lmax = args.lmax if args.lmax is not None else 2 * nside - 1
+    dt = {"f32": torch.float32, "f64": torch.float64, "bf16": torch.bfloat16}[args.dtype]
+    print("[bench] grad nside=%d lmax=%d B=%d %s" % (nside, lmax, B, args.dtype), flush=True)
+    ct = torch.complex128 if args.dtype == "f64" else torch.complex64
+    alm0 = torch.tensor(synth.gaussian_alm(17853, B, lmax, "lp10"), dtype=ct, device=dev)
+    x = shtx.alm2map_raw(alm0, nside, lmax).to(dt).requires_grad_(True)
+    ls, _ = synth.lm_arrays(lmax)
+    wl = torch.tensor(1.0 / (ls + 1.0), device=dev, dtype=torch.float64 if args.dtype == "f64" else torch.float32)
+
+    def step():
+        x.grad = None
+        a = shtx.map2alm(x, lmax)
+        loss = (wl * (a.real ** 2 + a.imag ** 2)).sum()
+        loss.backward()
+        return a
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    L = _lib.lib()
+    L.shtx_profile_reset()
+    L.shtx_profile_enable(1)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    stream = torch.cuda.current_stream(dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        evs[i][0].record(stream)
+        step()
+        evs[i][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    L.shtx_profile_enable(0)
+    prof = _lib.profile_read()
+    lat = np.array([u.elapsed_time(v) for u, v in evs])
+    a = step().detach()
+    torch.cuda.synchronize()
+    out = {
+        "metric": "differentiable SHT: forward + spectral loss + adjoint backward, maps/s at Nside=%d lmax=%d B=%d"
+                  % (nside, lmax, B),
+        "value": round(B * args.steps / wall, 3),
+        "unit": "maps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1000.0 * wall / args.steps, 4),
+        "p50_ms": round(float(np.percentile(lat, 50)), 4),
+        "p99_ms": round(float(np.percentile(lat, 99)), 4),
+        "higher_is_better": True,
+        "dtype": args.dtype,
+        "data": "synthetic",
+        "stages_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in prof.items() if v[1]},
+        "config": {"workload": "healpix_sht_grad", "nside": nside, "lmax": lmax, "batch": B,
+                   "loss": "sum_l w_l sum_m |a_lm|^2, w_l = 1/(l+1)", "fields": "gaussian C_l=(l+10)^-2"},
+    }
+    if not args.no_cpu_baseline:
+        # the oracle on channel 0: forward of the timed map and the adjoint of
+        # the loss gradient of the step's own coefficients
+        print("[bench] oracle on channel 0 of the step", flush=True)
+        from oracle import _clib, sht
+        _clib.build()
+        f0 = x.detach()[0].double().cpu().numpy()
+        a0 = a[0].cpu().numpy().astype(np.complex128)
+        g0 = x.grad[0].double().cpu().numpy()
+        t1 = time.perf_counter()
+        a_ref = sht.map2alm(f0[None, :], lmax, nside)[0]
+        g_ref = sht.map2alm_backward(sht.spectral_loss_grad(a0[None, :], lmax), nside, lmax)[0]
+        dt_o = time.perf_counter() - t1
+        out["accuracy_vs_oracle"] = {"map2alm_rel_l2": float("%.3e" % rel_l2(a0, a_ref)),
+                                     "grad_map_rel_l2": float("%.3e" % rel_l2(g0, g_ref)),
+                                     "oracle": "FP64 CPU oracle on channel 0 of the timed step"}
+        out["cpu_baseline"] = dict(value=round(1.0 / dt_o, 5), unit="maps/s", cores=_clib.threads(), kind="oracle",
+                                   sample="channel 0: oracle forward + adjoint, %.1f s" % dt_o)
+    print(json.dumps(out), flush=True)
+
+
 def run_peaks():
     """Measured counterparts of the published peaks: a 4 GiB device copy
     (HBM read + write) and large GEMMs in FP32, FP64 and BF16 (library
@@ -431,6 +521,62 @@ def run_reorder(args):
     print(json.dumps(out), flush=True)
 
 
+def run_nested(args):
+    """Analysis of NESTED-ordered maps (default Nside 1024, lmax 2047, B 16,
+    FP32): the layout conversion fused into the ring FFT's loads
+    (map2alm_nested) against the two passes nest2ring + map2alm, and the ring
+    FFT's time with NESTED against RING input (HIP events on the stream)."""
+    import torch
+    import paper_2510_01785_amd as shtx
+    from paper_2510_01785_amd import _lib
+    dev = torch.device("cuda:0")
+    nside, B = args.nside, args.batch
+    lmax = args.lmax if args.lmax is not None else 2 * nside - 1
+    dt = {"f32": torch.float32, "f64": torch.float64, "bf16": torch.bfloat16}[args.dtype]
+    print("[bench] nested-input analysis nside=%d lmax=%d B=%d %s" % (nside, lmax, B, args.dtype), flush=True)
+    xr = torch.randn((B, 12 * nside * nside), device=dev, dtype=torch.float32).to(dt)
+    xn = shtx.ring2nest(xr)
+    shtx.get_tables(nside, lmax, dev)
+    L = _lib.lib()
+    res = {}
+    for name, fn in (("fused", lambda: shtx.map2alm_nested_raw(xn, lmax)),
+                     ("two_pass", lambda: shtx.map2alm_raw(shtx.nest2ring(xn), lmax)),
+                     ("ring_input", lambda: shtx.map2alm_raw(xr, lmax))):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        L.shtx_profile_reset()
+        L.shtx_profile_enable(1)
+        evs = []
+        for _ in range(args.steps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            evs.append((e0, e1))
+        torch.cuda.synchronize()
+        L.shtx_profile_enable(0)
+        prof = _lib.profile_read()
+        res[name] = {"ms_per_call": round(float(np.median([a.elapsed_time(b) for a, b in evs])), 4),
+                     "ring_fft_fwd_ms": round(prof["ring_fft_fwd"][0] / max(prof["ring_fft_fwd"][1], 1), 4)}
+    out = {
+        "metric": "map2alm of NESTED maps, fused layout conversion vs nest2ring + map2alm, Nside=%d lmax=%d B=%d"
+                  % (nside, lmax, B),
+        "value": round(B / (res["fused"]["ms_per_call"] * 1e-3), 3),
+        "unit": "maps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "higher_is_better": True,
+        "dtype": args.dtype,
+        "data": "synthetic",
+        "calls": res,
+        "fft_nested_over_ring": round(res["fused"]["ring_fft_fwd_ms"] / res["ring_input"]["ring_fft_fwd_ms"], 4),
+        "config": {"workload": "healpix_map2alm_nested", "nside": nside, "lmax": lmax, "batch": B},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def run_resize(args):
     """Spectral resize of B coefficient sets from lmax = 2 nside - 1 to
     4 nside - 1 (default 2047 -> 4095, B=16, FP32): HBM-bound copy with zero
@@ -508,6 +654,10 @@ def main():
         return run_reorder(args)
     if args.workload == "resize":
         return run_resize(args)
+    if args.workload == "grad":
+        return run_grad(args)
+    if args.workload == "nested":
+        return run_nested(args)
     import paper_2510_01785_amd as shtx
     from paper_2510_01785_amd import _lib, synth
 

@@ -62,6 +62,15 @@ def nest_to_ring_index(nside, ipnest):
     ipf = p % (N * N)
     x = _deinterleave(ipf)
     y = _deinterleave(ipf >> 1)
+    return ring_index_of_xyf(N, x, y, f)
+
+
+def ring_index_of_xyf(nside, x, y, f):
+    """RING index of the pixel with face coordinates (x, y) on face f."""
+    N = int(nside)
+    x = np.asarray(x, dtype=np.int64)
+    y = np.asarray(y, dtype=np.int64)
+    f = np.asarray(f, dtype=np.int64)
     i = _RING_CORNER[f] * N - x - y - 1
     npix = 12 * N * N
     north = i < N

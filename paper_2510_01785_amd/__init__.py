@@ -6,10 +6,10 @@ input generators.  Importing it does not load the library: the first call of
 a transform does, and raises if it has not been built.
 """
 
-_LAZY = ("map2alm", "alm2map", "map2alm_raw", "alm2map_raw", "map2alm_backward_raw",
+_LAZY = ("map2alm", "alm2map", "map2alm_raw", "map2alm_nested_raw", "alm2map_raw", "map2alm_backward_raw",
          "alm2map_backward_raw", "map2alm_iter", "Map2Alm", "Alm2Map", "get_tables", "tables_work",
          "clear_tables",
-         "workspace_bytes", "nalm", "npix", "nside_of", "nest2ring", "ring2nest", "alm_resize",
+         "workspace_bytes", "nalm", "npix", "nside_of", "nest2ring", "ring2nest", "reorder", "alm_resize",
          "map2alm_weighted_raw")
 
 

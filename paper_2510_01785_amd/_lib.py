@@ -13,7 +13,9 @@ EXPORTS = ("shtx_version", "shtx_status_string", "shtx_tables_bytes", "shtx_tabl
            "shtx_map2alm_backward", "shtx_alm2map_backward", "shtx_iter_workspace_bytes",
            "shtx_map2alm_iter", "shtx_profile_enable",
            "shtx_profile_reset", "shtx_profile_read", "shtx_stage_name", "shtx_nest2ring", "shtx_ring2nest",
-           "shtx_alm_resize", "shtx_map2alm_weighted")
+           "shtx_alm_resize", "shtx_map2alm_weighted", "shtx_reorder", "shtx_map2alm_nested")
+LAYOUT_RING, LAYOUT_NESTED, LAYOUT_FLAT = 0, 1, 2
+FLAT_ORIGINS = ("S", "E", "N", "W")
 STAGES = ("ring_fft_fwd", "legendre_fwd", "alm_in", "legendre_inv", "ring_fft_inv")
 
 _lib = None
@@ -50,7 +52,8 @@ def lib():
     L.shtx_tables_work.restype = i
     L.shtx_workspace_bytes.argtypes = [i, i, i, i]
     L.shtx_workspace_bytes.restype = sz
-    for name in ("shtx_map2alm", "shtx_alm2map", "shtx_map2alm_backward", "shtx_alm2map_backward"):
+    for name in ("shtx_map2alm", "shtx_alm2map", "shtx_map2alm_backward", "shtx_alm2map_backward",
+                 "shtx_map2alm_nested"):
         f = getattr(L, name)
         f.argtypes = [i, i, i, i, vp, vp, vp, vp, sz, vp]
         f.restype = i
@@ -70,6 +73,8 @@ def lib():
     L.shtx_map2alm_weighted.restype = i
     L.shtx_alm_resize.argtypes = [i, i, i, i, vp, vp, vp]
     L.shtx_alm_resize.restype = i
+    L.shtx_reorder.argtypes = [i, i, i, i, i, vp, vp, vp]
+    L.shtx_reorder.restype = i
     for name in ("shtx_nest2ring", "shtx_ring2nest"):
         f = getattr(L, name)
         f.argtypes = [i, i, i, vp, vp, vp]
@@ -88,6 +93,18 @@ def profile_read():
         check("shtx_profile_read", L.shtx_profile_read(s, ctypes.byref(ms), ctypes.byref(n)))
         out[name] = (ms.value, n.value)
     return out
+
+
+def layout_code(layout):
+    """"ring", "nested" or ("flat", origin in "SENW", clockwise) -> ABI code."""
+    if layout == "ring":
+        return LAYOUT_RING
+    if layout == "nested":
+        return LAYOUT_NESTED
+    kind, origin, clockwise = layout
+    if kind != "flat" or origin not in FLAT_ORIGINS:
+        raise ValueError("unknown layout %r" % (layout,))
+    return LAYOUT_FLAT + 2 * FLAT_ORIGINS.index(origin) + int(bool(clockwise))
 
 
 def check(fn, status):

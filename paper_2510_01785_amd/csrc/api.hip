@@ -15,7 +15,7 @@ namespace shtx {
 
 hipError_t launch_tables_build(int nside, int lmax, void *base, hipStream_t st);
 template <typename TIn, typename T, typename TS>
-hipError_t launch_ring_fft_fwd(Tables, int, const TIn *, const double *, double, TS *, TS *, hipStream_t);
+hipError_t launch_ring_fft_fwd(Tables, int, const TIn *, const double *, double, TS *, TS *, hipStream_t, bool);
 hipError_t launch_legendre_fwd_bf16(const Tables &, int, const uint32_t *, const uint32_t *, float2 *, double, double,
                                     int, hipStream_t);
 template <typename TOut, typename T>
@@ -214,7 +214,7 @@ template <typename TIn> bool bf16_contraction(const Tables &tb, int B) {
 // analysis chain: ring FFT -> Legendre -> caller layout with factors
 template <typename TIn, typename T>
 int run_analysis(const Tables &tb, int B, const TIn *map, cplx<T> *alm, const double *wtab, double wscale,
-                 double f0, double fm, void *work, hipStream_t st, int accumulate = 0) {
+                 double f0, double fm, void *work, hipStream_t st, int accumulate = 0, bool nested = false) {
   Work<T> w = carve<T>(work, tb, B);
   hipError_t e;
   if constexpr (std::is_same<T, float>::value) {
@@ -222,7 +222,7 @@ int run_analysis(const Tables &tb, int B, const TIn *map, cplx<T> *alm, const do
       uint32_t *sa = reinterpret_cast<uint32_t *>(w.specA), *sb = reinterpret_cast<uint32_t *>(w.specB);
       {
         StageTimer t(kStFftFwd, st);
-        e = launch_ring_fft_fwd<TIn, T, uint32_t>(tb, B, map, wtab, wscale, sa, sb, st);
+        e = launch_ring_fft_fwd<TIn, T, uint32_t>(tb, B, map, wtab, wscale, sa, sb, st, nested);
       }
       if (e != hipSuccess) return SHTX_ERR_HIP;
       StageTimer t(kStLegFwd, st);
@@ -231,7 +231,7 @@ int run_analysis(const Tables &tb, int B, const TIn *map, cplx<T> *alm, const do
   }
   {
     StageTimer t(kStFftFwd, st);
-    e = launch_ring_fft_fwd<TIn, T, cplx<T>>(tb, B, map, wtab, wscale, w.specA, w.specB, st);
+    e = launch_ring_fft_fwd<TIn, T, cplx<T>>(tb, B, map, wtab, wscale, w.specA, w.specB, st, nested);
   }
   if (e != hipSuccess) return SHTX_ERR_HIP;
   StageTimer t(kStLegFwd, st);
@@ -385,6 +385,25 @@ int shtx_map2alm(int nside, int lmax, int batch, int dtype, const void *map, voi
     default:
       return run_analysis<bf16_t, float>(tb, batch, static_cast<const bf16_t *>(map), static_cast<float2 *>(alm),
                                          tb.rp_w, 1.0, 1.0, 1.0, work, st);
+  }
+}
+
+int shtx_map2alm_nested(int nside, int lmax, int batch, int dtype, const void *map_nest, void *alm,
+                        const void *tables, void *work, size_t work_bytes, void *stream) {
+  Tables tb;
+  int s = check_common(nside, lmax, batch, dtype, map_nest, alm, tables, work, work_bytes, &tb, true);
+  if (s != SHTX_OK) return s;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  switch (dtype) {
+    case SHTX_F64:
+      return run_analysis<double, double>(tb, batch, static_cast<const double *>(map_nest),
+                                          static_cast<double2 *>(alm), tb.rp_w, 1.0, 1.0, 1.0, work, st, 0, true);
+    case SHTX_F32:
+      return run_analysis<float, float>(tb, batch, static_cast<const float *>(map_nest), static_cast<float2 *>(alm),
+                                        tb.rp_w, 1.0, 1.0, 1.0, work, st, 0, true);
+    default:
+      return run_analysis<bf16_t, float>(tb, batch, static_cast<const bf16_t *>(map_nest),
+                                         static_cast<float2 *>(alm), tb.rp_w, 1.0, 1.0, 1.0, work, st, 0, true);
   }
 }
 

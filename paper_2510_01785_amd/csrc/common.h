@@ -160,6 +160,7 @@ struct TableOffsets {
   size_t ck_pos;                              // int32 [L+1]: item index of (m, l0 = m)
   size_t ck_t;                                // uint8 [I * Rp]: start offset in block (kBlockL: idle)
   size_t ck_v;                                // double2 [I * Rp]: (mu_{l-1}, mu_l) at that start
+  size_t r2n;                                 // uint32 [Npix]: NESTED index of each RING pixel
   size_t total;
   size_t nitems;
   size_t nbhat;
@@ -209,6 +210,7 @@ inline TableOffsets table_offsets(int nside, int lmax) {
   o.ck_pos = take((size_t)(lmax + 1) * 4);
   o.ck_t = take(o.nitems * Rp);
   o.ck_v = take(o.nitems * Rp * 16);
+  o.r2n = take(12 * (size_t)nside * (size_t)nside * 4);
   o.total = off;
   return o;
 }
@@ -228,6 +230,7 @@ struct Tables {
   const int *ck_xoff, *ck_pos;
   const uint8_t *ck_t;
   const double2 *ck_v;
+  const uint32_t *r2n;
 };
 
 inline Tables tables_view(const void *base, int nside, int lmax) {
@@ -267,6 +270,7 @@ inline Tables tables_view(const void *base, int nside, int lmax) {
   t.ck_pos = reinterpret_cast<const int *>(b + o.ck_pos);
   t.ck_t = reinterpret_cast<const uint8_t *>(b + o.ck_t);
   t.ck_v = reinterpret_cast<const double2 *>(b + o.ck_v);
+  t.r2n = reinterpret_cast<const uint32_t *>(b + o.r2n);
   return t;
 }
 

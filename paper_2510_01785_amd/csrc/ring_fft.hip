@@ -650,6 +650,26 @@ __device__ __forceinline__ bool fft_work(int Rp, int B, int G, int *p, int *b0, 
   return true;
 }
 
+// The same for maps in NESTED order (the analysis reads them in place, the
+// RING order of Sec. III-B applied to its loads): ring pairs in bands of
+// kNestBand consecutive pairs, bands dealt round-robin to the XCDs, so that
+// the neighbouring rings that share the 128-byte lines of a NESTED map
+// (a line holds an 8 x 4 block of a face, which spans 11 rings) are read by
+// one XCD close in time and meet in its L2.
+constexpr int kNestBand = 32;
+__device__ __forceinline__ bool fft_work_banded(int Rp, int B, int G, int *p, int *b0, int *b1) {
+  const int ncg = (B + G - 1) / G;
+  const int g = blockIdx.x;
+  const int x = g & 7, k = g >> 3;
+  const int t = k / ncg, cg = k % ncg;
+  const int pp = ((t / kNestBand) * 8 + x) * kNestBand + t % kNestBand;
+  if (pp >= Rp) return false;
+  *p = pp;
+  *b0 = cg * G;
+  *b1 = min(B, *b0 + G);
+  return true;
+}
+
 // Four consecutive map pixels as T (the caller guarantees 4-element
 // alignment of p: ring starts and lengths are multiples of 4 pixels).
 template <typename T, typename S> __device__ __forceinline__ void load4(const S *p, T (&v)[4]);
@@ -715,7 +735,23 @@ __device__ __forceinline__ void store_pair(uint32_t *p, float2 a, float2 b) {
 
 constexpr int kLoadUnroll = 2;  // quads of pixels in flight per thread
 
-template <typename TIn, typename T, typename TS, int NT>
+// Pixels j..j+3 of a ring (first pixel s) of one channel `row`: RING maps are
+// read as one vector, NESTED maps (NEST) pixel by pixel at the NESTED index
+// of each RING pixel (tables: r2n).
+template <bool NEST, typename T, typename TIn>
+__device__ __forceinline__ void load_ring4(const Tables &tb, const TIn *row, int s, int j, T (&v)[4]) {
+  if constexpr (NEST) {
+    const uint4 ix = *reinterpret_cast<const uint4 *>(tb.r2n + s + j);
+    v[0] = load_as<T, TIn>(row + ix.x);
+    v[1] = load_as<T, TIn>(row + ix.y);
+    v[2] = load_as<T, TIn>(row + ix.z);
+    v[3] = load_as<T, TIn>(row + ix.w);
+  } else {
+    load4<T, TIn>(row + s + j, v);
+  }
+}
+
+template <typename TIn, typename T, typename TS, bool NEST, int NT>
 __global__ void __launch_bounds__(NT, sizeof(T) == 4 ? 4 : 1)
     k_ring_fft_fwd(Tables tb, int B, int G, int tq_off, int bs_nb, const TIn *__restrict__ map,
                    const double *__restrict__ wtab, double wscale, TS *__restrict__ XE, TS *__restrict__ XO) {
@@ -724,7 +760,7 @@ __global__ void __launch_bounds__(NT, sizeof(T) == 4 ? 4 : 1)
   C *buf = reinterpret_cast<C *>(smem_raw);
   C *tq = buf + tq_off;
   int p, bg0, bg1;
-  if (!fft_work(tb.npairs, B, G, &p, &bg0, &bg1)) return;
+  if (!(NEST ? fft_work_banded(tb.npairs, B, G, &p, &bg0, &bg1) : fft_work(tb.npairs, B, G, &p, &bg0, &bg1))) return;
   const int n = tb.rp_n[p];
   const int sN = tb.rp_sN[p], sS = tb.rp_sS[p];
   const bool equator = (sN == sS);
@@ -745,7 +781,9 @@ __global__ void __launch_bounds__(NT, sizeof(T) == 4 ? 4 : 1)
       // Bluestein ring: samples read per sub-transform, packed on the fly
       auto input = [&](int c, int k) {
         const TIn *row = map + (size_t)(b0 + c) * npix;
-        const T a = load_as<T, TIn>(row + sN + k), b = equator ? (T)0 : load_as<T, TIn>(row + sS + k);
+        const int kN = NEST ? (int)tb.r2n[sN + k] : sN + k;
+        const int kS = NEST ? (int)tb.r2n[sS + k] : sS + k;
+        const T a = load_as<T, TIn>(row + kN), b = equator ? (T)0 : load_as<T, TIn>(row + kS);
         return cmk<C>(a + b, a - b);
       };
       ring_dft_bs4<T, NT>(tb, p, Mbs, bs_nb, gc, buf, tq, n, b0 != bg0, input);
@@ -760,9 +798,9 @@ __global__ void __launch_bounds__(NT, sizeof(T) == 4 ? 4 : 1)
           const int q = q0 + u * NT;
           if (q < gc * nq) {
             const int c = q / nq, j = 4 * (q - c * nq);
-            const TIn *row = map + (size_t)(b0 + c) * npix + j;
-            load4<T, TIn>(row + sN, fN[u]);
-            if (!equator) load4<T, TIn>(row + sS, fS[u]);
+            const TIn *row = map + (size_t)(b0 + c) * npix;
+            load_ring4<NEST, T, TIn>(tb, row, sN, j, fN[u]);
+            if (!equator) load_ring4<NEST, T, TIn>(tb, row, sS, j, fS[u]);
           }
         }
 #pragma unroll
@@ -1025,6 +1063,12 @@ inline unsigned fft_grid(int Rp, int B, int G) {
   const int ncg = (B + G - 1) / G;
   return 8u * (unsigned)((Rp + 7) / 8) * (unsigned)ncg;
 }
+// banded dealing (fft_work_banded): whole bands of kNestBand pairs per XCD
+inline unsigned fft_grid_banded(int Rp, int B, int G) {
+  const int ncg = (B + G - 1) / G;
+  const int bands_per_xcd = (Rp + 8 * kNestBand - 1) / (8 * kNestBand);
+  return 8u * (unsigned)(bands_per_xcd * kNestBand) * (unsigned)ncg;
+}
 
 template <typename K> hipError_t allow_lds(K kern, size_t lds) {
   if (lds <= 64 * 1024) return hipSuccess;
@@ -1033,14 +1077,15 @@ template <typename K> hipError_t allow_lds(K kern, size_t lds) {
 
 template <typename TIn, typename T, typename TS>
 hipError_t launch_ring_fft_fwd(Tables tb, int B, const TIn *map, const double *wtab, double wscale, TS *XE, TS *XO,
-                               hipStream_t st) {
+                               hipStream_t st, bool nested) {
   const FftGeom g = fft_geometry(tb.nside, tb.mmax_bs, B, sizeof(cplx<T>));
   if (g.lds > kMaxLds) return hipErrorInvalidValue;
-  auto kern = k_ring_fft_fwd<TIn, T, TS, kFftThreads>;
+  auto kern = nested ? k_ring_fft_fwd<TIn, T, TS, true, kFftThreads> : k_ring_fft_fwd<TIn, T, TS, false, kFftThreads>;
   hipError_t e = allow_lds(kern, g.lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(kern, dim3(fft_grid(tb.npairs, B, g.G)), dim3(kFftThreads), g.lds, st, tb, B, g.G, g.tq_off,
-                     g.bs_nb, map, wtab, wscale, XE, XO);
+  const unsigned grid = nested ? fft_grid_banded(tb.npairs, B, g.G) : fft_grid(tb.npairs, B, g.G);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(kFftThreads), g.lds, st, tb, B, g.G, g.tq_off, g.bs_nb, map, wtab, wscale,
+                     XE, XO);
   return hipGetLastError();
 }
 
@@ -1058,13 +1103,13 @@ hipError_t launch_ring_fft_inv(Tables tb, int B, const cplx<T> *GN, const cplx<T
 }
 
 template hipError_t launch_ring_fft_fwd<double, double, double2>(Tables, int, const double *, const double *, double,
-                                                                 double2 *, double2 *, hipStream_t);
+                                                                 double2 *, double2 *, hipStream_t, bool);
 template hipError_t launch_ring_fft_fwd<float, float, float2>(Tables, int, const float *, const double *, double,
-                                                              float2 *, float2 *, hipStream_t);
+                                                              float2 *, float2 *, hipStream_t, bool);
 template hipError_t launch_ring_fft_fwd<bf16_t, float, float2>(Tables, int, const bf16_t *, const double *, double,
-                                                               float2 *, float2 *, hipStream_t);
+                                                               float2 *, float2 *, hipStream_t, bool);
 template hipError_t launch_ring_fft_fwd<bf16_t, float, uint32_t>(Tables, int, const bf16_t *, const double *,
-                                                                 double, uint32_t *, uint32_t *, hipStream_t);
+                                                                 double, uint32_t *, uint32_t *, hipStream_t, bool);
 template hipError_t launch_ring_fft_inv<double, double>(Tables, int, const double2 *, const double2 *,
                                                         const double *, double *, hipStream_t);
 template hipError_t launch_ring_fft_inv<float, float>(Tables, int, const float2 *, const float2 *, const float *,

@@ -314,6 +314,46 @@ __global__ void k_checkpoints(int L, int Rp, const double *zarr, const double *c
   }
 }
 
+// One thread per NESTED pixel p = f N^2 + interleave(x, y) (x in the even
+// bits): its RING index from the face's corner ring rf and longitude position
+// qf (HEALPix grid definition, Sec. III-A/III-B): ring i = rf N - x - y - 1,
+// 1-based slot j = (qf n + x - y + 1 + s) / 2 cyclic in 1..4n, with n = i,
+// 4N - i or N pixels per quadrant (north cap, south cap, belt) and belt shift
+// s = (i - N) mod 2; r2n[RING index] = p.
+__global__ void k_ring2nest_table(int lgn, uint32_t *r2n) {
+  const uint32_t N = 1u << lgn, npix = 12u << (2 * lgn);
+  const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= npix) return;
+  const uint32_t f = p >> (2 * lgn), q = p & ((1u << (2 * lgn)) - 1u);
+  uint32_t x = q & 0x55555555u, y = (q >> 1) & 0x55555555u;
+  for (int k = 1; k < 16; k <<= 1) {  // compact the even bits
+    const uint32_t m = k == 1 ? 0x33333333u : k == 2 ? 0x0f0f0f0fu : k == 4 ? 0x00ff00ffu : 0x0000ffffu;
+    x = (x | (x >> k)) & m;
+    y = (y | (y >> k)) & m;
+  }
+  const int row = (int)(f >> 2), rf = row + 2, qf = 2 * (int)(f & 3u) + (row != 1);
+  const int i = rf * (int)N - (int)x - (int)y - 1;
+  int n, s;
+  uint32_t start;
+  if (i < (int)N) {
+    n = i;
+    s = 0;
+    start = 2u * (uint32_t)i * (uint32_t)(i - 1);
+  } else if (i > 3 * (int)N) {
+    n = 4 * (int)N - i;
+    s = 0;
+    start = npix - 2u * (uint32_t)n * (uint32_t)(n + 1);
+  } else {
+    n = (int)N;
+    s = (i - (int)N) & 1;
+    start = 2u * N * (N - 1u) + 4u * N * (uint32_t)(i - (int)N);
+  }
+  int j = (qf * n + (int)x - (int)y + 1 + s) >> 1;
+  if (j > 4 * n) j -= 4 * n;
+  if (j < 1) j += 4 * n;
+  r2n[start + (uint32_t)(j - 1)] = p;
+}
+
 hipError_t launch_tables_build(int nside, int lmax, void *base, hipStream_t st) {
   const TableOffsets o = table_offsets(nside, lmax);
   char *b = static_cast<char *>(base);
@@ -324,6 +364,11 @@ hipError_t launch_tables_build(int nside, int lmax, void *base, hipStream_t st) 
                      I(o.rp_sS), I(o.rp_p0n), I(o.rp_p0d), I(o.rp_M), I(o.rp_bsoff), D(o.rp_z), D(o.rp_sth),
                      D(o.rp_w));
   hipLaunchKernelGGL(k_coefs, dim3((lmax + 1 + 63) / 64), dim3(64), 0, st, lmax, D(o.coefA), D(o.coefC));
+  {
+    const uint32_t npix = 12u * (uint32_t)nside * (uint32_t)nside;
+    hipLaunchKernelGGL(k_ring2nest_table, dim3((npix + 255) / 256), dim3(256), 0, st, __builtin_ctz((unsigned)nside),
+                       reinterpret_cast<uint32_t *>(b + o.r2n));
+  }
   double2 *sv = reinterpret_cast<double2 *>(b + o.seed_v);
   hipLaunchKernelGGL(k_lambda_mm, dim3((Rp + 63) / 64), dim3(64), 0, st, lmax, Rp, D(o.rp_sth), sv);
   hipLaunchKernelGGL(k_seeds, dim3((Rp + 63) / 64, lmax + 1), dim3(64), 0, st, lmax, Rp, D(o.rp_z),

@@ -112,6 +112,18 @@ def map2alm_raw(maps, lmax):
     return _call("shtx_map2alm", nside, lmax, B, code, maps, out, maps.device)
 
 
+def map2alm_nested_raw(maps_nest, lmax):
+    """maps [B, Npix] in NESTED order -> alm [B, nalm] (the layout conversion
+    fused into the analysis' loads); no autograd."""
+    _check_device(maps_nest)
+    code = _DTYPES[maps_nest.dtype]
+    maps_nest = maps_nest.contiguous()
+    B, n = maps_nest.shape
+    nside = nside_of(n)
+    out = torch.empty((B, nalm(lmax)), dtype=_ALM_DTYPE[code], device=maps_nest.device)
+    return _call("shtx_map2alm_nested", nside, lmax, B, code, maps_nest, out, maps_nest.device)
+
+
 def alm2map_raw(alm, nside, lmax):
     """alm [B, nalm] complex128/complex64 -> maps [B, Npix] float64/float32."""
     _check_device(alm)
@@ -220,6 +232,21 @@ def _reorder(fn, maps):
     nside = nside_of(n)
     out = torch.empty_like(x)
     _lib.check(fn, getattr(_lib.lib(), fn)(nside, B, code, x.data_ptr(), out.data_ptr(), _stream_ptr(x.device)))
+    return out[0] if squeeze else out
+
+
+def reorder(maps, src, dst):
+    """Maps [..., Npix] from pixel layout `src` to layout `dst`, each "ring",
+    "nested" or ("flat", origin in "SENW", clockwise)."""
+    _check_device(maps)
+    x, squeeze = _as_batched(maps)
+    code = _DTYPES[x.dtype]
+    x = x.contiguous()
+    B, n = x.shape
+    nside = nside_of(n)
+    out = torch.empty_like(x)
+    _lib.check("shtx_reorder", _lib.lib().shtx_reorder(nside, B, code, _lib.layout_code(src), _lib.layout_code(dst),
+                                                       x.data_ptr(), out.data_ptr(), _stream_ptr(x.device)))
     return out[0] if squeeze else out
 
 

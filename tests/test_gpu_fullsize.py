@@ -133,6 +133,29 @@ def test_map2alm_fullsize_bf16_input(shtx, monkeypatch):
     assert err32 <= 1e-5
 
 
+def test_loss_gradient_fullsize_nside1024_b16(shtx):
+    """The differentiable workload at full size (Nside 1024, lmax 2047, 16
+    FP32 channels): autograd of the spectral loss sum_l w_l sum_m |a_lm|^2
+    (w_l = 1/(l+1)) through the adjoint kernels, against the oracle's adjoint
+    of the same upstream gradient (2 w_l a_lm of the forward's own output),
+    every pixel of the gradient map."""
+    nside, lmax, B = 1024, 2047, 16
+    announce("loss gradient full size nside=%d lmax=%d B=%d f32" % (nside, lmax, B))
+    f = f32_map(8400, B, nside)
+    x = torch.tensor(f, dtype=torch.float32, device="cuda", requires_grad=True)
+    a = shtx.map2alm(x, lmax)
+    ls, _ = synth.lm_arrays(lmax)
+    w = torch.tensor(1.0 / (ls + 1.0), device="cuda", dtype=torch.float32)
+    (w * (a.real ** 2 + a.imag ** 2)).sum().backward()
+    a_gpu = a.detach().cpu().numpy().astype(np.complex128)
+    g = x.grad.double().cpu().numpy()
+    del x, a
+    ref = sht.map2alm_backward(sht.spectral_loss_grad(a_gpu, lmax), nside, lmax)
+    err = rel_l2(g, ref)
+    print("[fullsize] loss gradient nside 1024 B 16 f32 rel l2 %.3e" % err, flush=True)
+    assert err <= TOL[torch.float32]
+
+
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 def test_jacobi_parity_nside512(shtx, dtype):
     """Refined analysis with 3 iterations (4 forward, 3 inverse transforms)

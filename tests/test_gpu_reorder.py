@@ -86,3 +86,71 @@ def test_nested_map_through_the_transform(shtx):
     a = shtx.map2alm_raw(shtx.nest2ring(torch.tensor(f_nest, device="cuda:0")), lmax).cpu().numpy()
     ref = sht.map2alm(f, lmax, nside)
     assert np.linalg.norm(a - ref) / np.linalg.norm(ref) < 1e-12
+
+
+def all_layouts():
+    from oracle import layouts
+    return layouts.all_layouts()
+
+
+@pytest.mark.parametrize("nside", [1, 2, 4, 16, 64, 128])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32, torch.bfloat16])
+def test_reorder_any_layout_parity(shtx, nside, dtype):
+    """Every pair of RING, NESTED and the eight FLAT orientations (Sec. III-B,
+    two-step conversion through (x, y, f)) against the oracle's conversion:
+    bit-exact; nside 128 has two 64 x 64 squares per face side."""
+    from oracle import layouts
+    announce("reorder any layout nside=%d %s" % (nside, dtype))
+    g = torch.Generator().manual_seed(2000 + nside)
+    x = torch.randn((2, 12 * nside * nside), generator=g, dtype=torch.float64).to(dtype)
+    xb = bits(x)
+    xd = x.cuda()
+    for src in all_layouts():
+        for dst in all_layouts():
+            got = bits(shtx.reorder(xd, src, dst))
+            assert np.array_equal(got, layouts.convert(xb, nside, src, dst)), (src, dst)
+
+
+def test_reorder_flat_fullsize_sampled(shtx):
+    """Nside 1024, 4 FP32 channels: RING -> FLAT (origin E, clockwise) -> NESTED
+    -> RING round trip is the identity, and 100k sampled FLAT pixels hold the
+    RING pixel the oracle's (x, y, f) mapping names."""
+    from oracle import layouts
+    nside, B = 1024, 4
+    announce("reorder flat full size nside=%d B=%d" % (nside, B))
+    x = torch.randn((B, 12 * nside * nside), device="cuda", dtype=torch.float32)
+    lay = ("flat", "E", True)
+    fl = shtx.reorder(x, "ring", lay)
+    back = shtx.reorder(shtx.reorder(fl, lay, "nested"), "nested", "ring")
+    assert torch.equal(back, x)
+    rng = np.random.default_rng(3)
+    idx = rng.integers(0, 12 * nside * nside, 100000)
+    xx, yy, ff = layouts.xyf_of_index(nside, lay, idx)
+    ring = layouts.index_of_xyf(nside, "ring", xx, yy, ff)
+    xs, fls = x.cpu().numpy(), fl.cpu().numpy()
+    assert np.array_equal(fls[:, idx], xs[:, ring])
+
+
+@pytest.mark.parametrize("nside,lmax,batch,dtype", [(4, 11, 2, torch.float64), (16, 47, 3, torch.float64),
+                                                    (64, 191, 16, torch.float32), (128, 383, 5, torch.float32),
+                                                    (32, 95, 16, torch.bfloat16), (256, 511, 2, torch.float32)])
+def test_map2alm_nested_input(shtx, nside, lmax, batch, dtype):
+    """Analysis of NESTED-ordered maps with the layout conversion fused into
+    the ring FFT's loads: bit-identical to nest2ring followed by map2alm, and
+    within the dtype tolerance of the oracle's analysis of the oracle's RING
+    reordering."""
+    from oracle import geometry, sht
+    from paper_2510_01785_amd import synth
+    announce("map2alm nested input nside=%d lmax=%d B=%d %s" % (nside, lmax, batch, dtype))
+    f_ring = synth.white_map(4400 + nside, batch, geometry.npix(nside))
+    f_nest = nested.ring_to_nest(f_ring, nside)
+    xn = torch.tensor(f_nest, dtype=torch.float32 if dtype == torch.bfloat16 else dtype).to(dtype).cuda()
+    got = shtx.map2alm_nested_raw(xn, lmax)
+    two_pass = shtx.map2alm_raw(shtx.nest2ring(xn), lmax)
+    torch.cuda.synchronize()
+    assert torch.equal(got, two_pass)
+    ref = sht.map2alm(nested.nest_to_ring(xn.double().cpu().numpy(), nside), lmax, nside)
+    g = got.cpu().numpy()
+    err = np.linalg.norm((g - ref).ravel()) / np.linalg.norm(ref.ravel())
+    tol = {torch.float64: 1e-12, torch.float32: 1e-5, torch.bfloat16: 2.5 * 2.0 ** -8}[dtype]
+    assert err <= tol
