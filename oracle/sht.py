@@ -86,12 +86,21 @@ def _ring_inverse(g, r, Gr):
     return f.real.T
 
 
-def map2alm(maps, lmax, nside=None, ring_weights=None, nthreads=None):
-    """Forward SHT of real RING maps [B, Npix] -> complex alm [B, nalm]."""
+def map2alm(maps, lmax, nside=None, ring_weights=None, nthreads=None, pixel_weights=None):
+    """Forward SHT of real RING maps [B, Npix] -> complex alm [B, nalm].
+
+    Quadrature weights (the schemes of Sec. IV-A): equal 4 pi / Npix by
+    default; ring_weights [R] gives one weight per ring; pixel_weights [Npix]
+    (RING order) one weight per pixel, a_lm = sum_p w_p f_p conj(Y_lm(p)) (the
+    ring weights, if also given, multiply it; otherwise they are 1)."""
     maps = np.atleast_2d(np.asarray(maps, dtype=np.float64))
     if nside is None:
         nside = int(round(np.sqrt(maps.shape[1] / 12)))
     g = geometry.ring_geometry(nside)
+    if pixel_weights is not None:
+        maps = maps * np.asarray(pixel_weights, dtype=np.float64)[None, :]
+        if ring_weights is None:
+            ring_weights = np.ones(geometry.nrings(nside))
     F = ring_fourier_forward(maps, nside, lmax, ring_weights)
     return legendre_analysis(lmax, g["z"], g["sth"], F, nthreads)
 
@@ -188,18 +197,22 @@ def alm2map_backward(grad_map, lmax, nside=None, nthreads=None):
     return out
 
 
-def jacobi_map2alm(maps, lmax, nside, niter=3, nthreads=None):
-    """Iterative refinement of Eq. (4): a <- a + A(f - S a), niter times.
+def jacobi_map2alm(maps, lmax, nside, niter=3, nthreads=None, ring_weights=None, pixel_weights=None):
+    """Iterative refinement of Eq. (4): a <- a + A(f - S a), niter times,
+    with A the analysis of the given quadrature weights (equal by default).
 
     Returns the list [a^0, a^1, ..., a^niter] (niter+1 forward and niter
     inverse transforms).
     """
     maps = np.atleast_2d(np.asarray(maps, dtype=np.float64))
-    a = map2alm(maps, lmax, nside, nthreads=nthreads)
+
+    def A(f):
+        return map2alm(f, lmax, nside, ring_weights=ring_weights, nthreads=nthreads, pixel_weights=pixel_weights)
+    a = A(maps)
     out = [a]
     for _ in range(niter):
         r = maps - alm2map(a, nside, lmax, nthreads)
-        a = a + map2alm(r, lmax, nside, nthreads=nthreads)
+        a = a + A(r)
         out.append(a)
     return out
 

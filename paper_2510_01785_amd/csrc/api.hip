@@ -15,7 +15,8 @@ namespace shtx {
 
 hipError_t launch_tables_build(int nside, int lmax, void *base, hipStream_t st);
 template <typename TIn, typename T, typename TS>
-hipError_t launch_ring_fft_fwd(Tables, int, const TIn *, const double *, double, TS *, TS *, hipStream_t, bool);
+hipError_t launch_ring_fft_fwd(Tables, int, const TIn *, const double *, double, const double *, TS *, TS *,
+                               hipStream_t, bool);
 hipError_t launch_legendre_fwd_bf16(const Tables &, int, const uint32_t *, const uint32_t *, float2 *, double, double,
                                     int, hipStream_t);
 template <typename TOut, typename T>
@@ -214,7 +215,8 @@ template <typename TIn> bool bf16_contraction(const Tables &tb, int B) {
 // analysis chain: ring FFT -> Legendre -> caller layout with factors
 template <typename TIn, typename T>
 int run_analysis(const Tables &tb, int B, const TIn *map, cplx<T> *alm, const double *wtab, double wscale,
-                 double f0, double fm, void *work, hipStream_t st, int accumulate = 0, bool nested = false) {
+                 double f0, double fm, void *work, hipStream_t st, int accumulate = 0, bool nested = false,
+                 const double *pixw = nullptr) {
   Work<T> w = carve<T>(work, tb, B);
   hipError_t e;
   if constexpr (std::is_same<T, float>::value) {
@@ -222,7 +224,7 @@ int run_analysis(const Tables &tb, int B, const TIn *map, cplx<T> *alm, const do
       uint32_t *sa = reinterpret_cast<uint32_t *>(w.specA), *sb = reinterpret_cast<uint32_t *>(w.specB);
       {
         StageTimer t(kStFftFwd, st);
-        e = launch_ring_fft_fwd<TIn, T, uint32_t>(tb, B, map, wtab, wscale, sa, sb, st, nested);
+        e = launch_ring_fft_fwd<TIn, T, uint32_t>(tb, B, map, wtab, wscale, pixw, sa, sb, st, nested);
       }
       if (e != hipSuccess) return SHTX_ERR_HIP;
       StageTimer t(kStLegFwd, st);
@@ -231,7 +233,7 @@ int run_analysis(const Tables &tb, int B, const TIn *map, cplx<T> *alm, const do
   }
   {
     StageTimer t(kStFftFwd, st);
-    e = launch_ring_fft_fwd<TIn, T, cplx<T>>(tb, B, map, wtab, wscale, w.specA, w.specB, st, nested);
+    e = launch_ring_fft_fwd<TIn, T, cplx<T>>(tb, B, map, wtab, wscale, pixw, w.specA, w.specB, st, nested);
   }
   if (e != hipSuccess) return SHTX_ERR_HIP;
   StageTimer t(kStLegFwd, st);
@@ -428,6 +430,27 @@ int shtx_map2alm_weighted(int nside, int lmax, int batch, int dtype, const void 
   }
 }
 
+int shtx_map2alm_pixel_weighted(int nside, int lmax, int batch, int dtype, const void *map, void *alm,
+                                const double *pixel_weights, const void *tables, void *work, size_t work_bytes,
+                                void *stream) {
+  if (!pixel_weights || (reinterpret_cast<uintptr_t>(pixel_weights) & 15)) return SHTX_ERR_ARG;
+  Tables tb;
+  int s = check_common(nside, lmax, batch, dtype, map, alm, tables, work, work_bytes, &tb, true);
+  if (s != SHTX_OK) return s;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  switch (dtype) {
+    case SHTX_F64:
+      return run_analysis<double, double>(tb, batch, static_cast<const double *>(map), static_cast<double2 *>(alm),
+                                          nullptr, 1.0, 1.0, 1.0, work, st, 0, false, pixel_weights);
+    case SHTX_F32:
+      return run_analysis<float, float>(tb, batch, static_cast<const float *>(map), static_cast<float2 *>(alm),
+                                        nullptr, 1.0, 1.0, 1.0, work, st, 0, false, pixel_weights);
+    default:
+      return run_analysis<bf16_t, float>(tb, batch, static_cast<const bf16_t *>(map), static_cast<float2 *>(alm),
+                                         nullptr, 1.0, 1.0, 1.0, work, st, 0, false, pixel_weights);
+  }
+}
+
 int shtx_alm2map(int nside, int lmax, int batch, int dtype, const void *alm, void *map, const void *tables,
                  void *work, size_t work_bytes, void *stream) {
   Tables tb;
@@ -484,36 +507,56 @@ size_t shtx_iter_workspace_bytes(int nside, int lmax, int batch, int dtype) {
   return base + align_up((size_t)batch * 12 * (size_t)nside * (size_t)nside * e, 256);
 }
 
+}  // extern "C"
+
+namespace shtx {
+namespace {
+// Refinement of Eq. (4)-(5) with the analysis A of the given quadrature
+// weights: a = A f, then niter times a += A (f - S a) (the residual is formed
+// in the synthesis' ring FFT store, the update in the analysis' accumulate
+// mode).
+template <typename T>
+int run_iter(const Tables &tb, int batch, const T *f, cplx<T> *a, int niter, const double *wtab,
+             const double *pixw, void *work, size_t resid_off, hipStream_t st) {
+  T *r = reinterpret_cast<T *>(static_cast<char *>(work) + resid_off);
+  int s = run_analysis<T, T>(tb, batch, f, a, wtab, 1.0, 1.0, 1.0, work, st, 0, false, pixw);
+  for (int k = 0; k < niter && s == SHTX_OK; ++k) {
+    s = run_synthesis<T, T>(tb, batch, a, r, 1.0, 1.0, 1.0, work, st, f);
+    if (s == SHTX_OK) s = run_analysis<T, T>(tb, batch, r, a, wtab, 1.0, 1.0, 1.0, work, st, 1, false, pixw);
+  }
+  return s;
+}
+}  // namespace
+}  // namespace shtx
+
+extern "C" {
+
 int shtx_map2alm_iter(int nside, int lmax, int batch, int dtype, const void *map, void *alm, int niter,
                       const void *tables, void *work, size_t work_bytes, void *stream) {
+  return shtx_map2alm_iter_weighted(nside, lmax, batch, dtype, map, alm, niter, nullptr, nullptr, tables, work,
+                                    work_bytes, stream);
+}
+
+int shtx_map2alm_iter_weighted(int nside, int lmax, int batch, int dtype, const void *map, void *alm, int niter,
+                               const double *ring_weights, const double *pixel_weights, const void *tables,
+                               void *work, size_t work_bytes, void *stream) {
   if (niter < 0 || niter > kMaxIter) return SHTX_ERR_ARG;
   if (dtype == SHTX_BF16) return SHTX_ERR_UNSUPPORTED;
+  if ((reinterpret_cast<uintptr_t>(ring_weights) & 7) || (reinterpret_cast<uintptr_t>(pixel_weights) & 15))
+    return SHTX_ERR_ARG;
   Tables tb;
   int s = check_common(nside, lmax, batch, dtype, map, alm, tables, work, work_bytes, &tb, true);
   if (s != SHTX_OK) return s;
   if (work_bytes < shtx_iter_workspace_bytes(nside, lmax, batch, dtype)) return SHTX_ERR_WORKSPACE;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  char *resid = static_cast<char *>(work) + shtx_workspace_bytes(nside, lmax, batch, dtype);
-  if (dtype == SHTX_F64) {
-    const double *f = static_cast<const double *>(map);
-    double2 *a = static_cast<double2 *>(alm);
-    double *r = reinterpret_cast<double *>(resid);
-    s = run_analysis<double, double>(tb, batch, f, a, tb.rp_w, 1.0, 1.0, 1.0, work, st);
-    for (int k = 0; k < niter && s == SHTX_OK; ++k) {
-      s = run_synthesis<double, double>(tb, batch, a, r, 1.0, 1.0, 1.0, work, st, f);
-      if (s == SHTX_OK) s = run_analysis<double, double>(tb, batch, r, a, tb.rp_w, 1.0, 1.0, 1.0, work, st, 1);
-    }
-    return s;
-  }
-  const float *f = static_cast<const float *>(map);
-  float2 *a = static_cast<float2 *>(alm);
-  float *r = reinterpret_cast<float *>(resid);
-  s = run_analysis<float, float>(tb, batch, f, a, tb.rp_w, 1.0, 1.0, 1.0, work, st);
-  for (int k = 0; k < niter && s == SHTX_OK; ++k) {
-    s = run_synthesis<float, float>(tb, batch, a, r, 1.0, 1.0, 1.0, work, st, f);
-    if (s == SHTX_OK) s = run_analysis<float, float>(tb, batch, r, a, tb.rp_w, 1.0, 1.0, 1.0, work, st, 1);
-  }
-  return s;
+  const size_t roff = shtx_workspace_bytes(nside, lmax, batch, dtype);
+  // ring weights: the caller's, 1 under pixel weights alone, else the equal 4 pi / Npix
+  const double *wtab = ring_weights ? ring_weights : pixel_weights ? nullptr : tb.rp_w;
+  if (dtype == SHTX_F64)
+    return run_iter<double>(tb, batch, static_cast<const double *>(map), static_cast<double2 *>(alm), niter, wtab,
+                            pixel_weights, work, roff, st);
+  return run_iter<float>(tb, batch, static_cast<const float *>(map), static_cast<float2 *>(alm), niter, wtab,
+                         pixel_weights, work, roff, st);
 }
 
 }  // extern "C"

@@ -751,10 +751,21 @@ __device__ __forceinline__ void load_ring4(const Tables &tb, const TIn *row, int
   }
 }
 
+// Per-pixel quadrature weights (RING order, FP64) on four consecutive pixels.
+template <typename T> __device__ __forceinline__ void weigh4(const double *pw, int s, int j, T (&v)[4]) {
+  const double2 a = *reinterpret_cast<const double2 *>(pw + s + j);
+  const double2 b = *reinterpret_cast<const double2 *>(pw + s + j + 2);
+  v[0] *= (T)a.x;
+  v[1] *= (T)a.y;
+  v[2] *= (T)b.x;
+  v[3] *= (T)b.y;
+}
+
 template <typename TIn, typename T, typename TS, bool NEST, int NT>
 __global__ void __launch_bounds__(NT, sizeof(T) == 4 ? 4 : 1)
     k_ring_fft_fwd(Tables tb, int B, int G, int tq_off, int bs_nb, const TIn *__restrict__ map,
-                   const double *__restrict__ wtab, double wscale, TS *__restrict__ XE, TS *__restrict__ XO) {
+                   const double *__restrict__ wtab, double wscale, const double *__restrict__ pixw,
+                   TS *__restrict__ XE, TS *__restrict__ XO) {
   using C = cplx<T>;
   extern __shared__ unsigned char smem_raw[];
   C *buf = reinterpret_cast<C *>(smem_raw);
@@ -783,7 +794,11 @@ __global__ void __launch_bounds__(NT, sizeof(T) == 4 ? 4 : 1)
         const TIn *row = map + (size_t)(b0 + c) * npix;
         const int kN = NEST ? (int)tb.r2n[sN + k] : sN + k;
         const int kS = NEST ? (int)tb.r2n[sS + k] : sS + k;
-        const T a = load_as<T, TIn>(row + kN), b = equator ? (T)0 : load_as<T, TIn>(row + kS);
+        T a = load_as<T, TIn>(row + kN), b = equator ? (T)0 : load_as<T, TIn>(row + kS);
+        if (pixw) {
+          a *= (T)pixw[sN + k];
+          if (!equator) b *= (T)pixw[sS + k];
+        }
         return cmk<C>(a + b, a - b);
       };
       ring_dft_bs4<T, NT>(tb, p, Mbs, bs_nb, gc, buf, tq, n, b0 != bg0, input);
@@ -801,6 +816,10 @@ __global__ void __launch_bounds__(NT, sizeof(T) == 4 ? 4 : 1)
             const TIn *row = map + (size_t)(b0 + c) * npix;
             load_ring4<NEST, T, TIn>(tb, row, sN, j, fN[u]);
             if (!equator) load_ring4<NEST, T, TIn>(tb, row, sS, j, fS[u]);
+            if (pixw) {
+              weigh4<T>(pixw, sN, j, fN[u]);
+              if (!equator) weigh4<T>(pixw, sS, j, fS[u]);
+            }
           }
         }
 #pragma unroll
@@ -1076,8 +1095,8 @@ template <typename K> hipError_t allow_lds(K kern, size_t lds) {
 }
 
 template <typename TIn, typename T, typename TS>
-hipError_t launch_ring_fft_fwd(Tables tb, int B, const TIn *map, const double *wtab, double wscale, TS *XE, TS *XO,
-                               hipStream_t st, bool nested) {
+hipError_t launch_ring_fft_fwd(Tables tb, int B, const TIn *map, const double *wtab, double wscale,
+                               const double *pixw, TS *XE, TS *XO, hipStream_t st, bool nested) {
   const FftGeom g = fft_geometry(tb.nside, tb.mmax_bs, B, sizeof(cplx<T>));
   if (g.lds > kMaxLds) return hipErrorInvalidValue;
   auto kern = nested ? k_ring_fft_fwd<TIn, T, TS, true, kFftThreads> : k_ring_fft_fwd<TIn, T, TS, false, kFftThreads>;
@@ -1085,7 +1104,7 @@ hipError_t launch_ring_fft_fwd(Tables tb, int B, const TIn *map, const double *w
   if (e != hipSuccess) return e;
   const unsigned grid = nested ? fft_grid_banded(tb.npairs, B, g.G) : fft_grid(tb.npairs, B, g.G);
   hipLaunchKernelGGL(kern, dim3(grid), dim3(kFftThreads), g.lds, st, tb, B, g.G, g.tq_off, g.bs_nb, map, wtab, wscale,
-                     XE, XO);
+                     pixw, XE, XO);
   return hipGetLastError();
 }
 
@@ -1103,13 +1122,15 @@ hipError_t launch_ring_fft_inv(Tables tb, int B, const cplx<T> *GN, const cplx<T
 }
 
 template hipError_t launch_ring_fft_fwd<double, double, double2>(Tables, int, const double *, const double *, double,
-                                                                 double2 *, double2 *, hipStream_t, bool);
+                                                                 const double *, double2 *, double2 *, hipStream_t,
+                                                                 bool);
 template hipError_t launch_ring_fft_fwd<float, float, float2>(Tables, int, const float *, const double *, double,
-                                                              float2 *, float2 *, hipStream_t, bool);
+                                                              const double *, float2 *, float2 *, hipStream_t, bool);
 template hipError_t launch_ring_fft_fwd<bf16_t, float, float2>(Tables, int, const bf16_t *, const double *, double,
-                                                               float2 *, float2 *, hipStream_t, bool);
+                                                               const double *, float2 *, float2 *, hipStream_t, bool);
 template hipError_t launch_ring_fft_fwd<bf16_t, float, uint32_t>(Tables, int, const bf16_t *, const double *,
-                                                                 double, uint32_t *, uint32_t *, hipStream_t, bool);
+                                                                 double, const double *, uint32_t *, uint32_t *,
+                                                                 hipStream_t, bool);
 template hipError_t launch_ring_fft_inv<double, double>(Tables, int, const double2 *, const double2 *,
                                                         const double *, double *, hipStream_t);
 template hipError_t launch_ring_fft_inv<float, float>(Tables, int, const float2 *, const float2 *, const float *,

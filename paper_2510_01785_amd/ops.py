@@ -298,3 +298,56 @@ def map2alm_weighted_raw(maps, lmax, ring_weights):
                L.shtx_map2alm_weighted(nside, lmax, B, code, maps.data_ptr(), out.data_ptr(), w.data_ptr(),
                                        tab.data_ptr(), work.data_ptr(), wb, _stream_ptr(maps.device)))
     return out
+
+
+# ------------------------------------------------------ pixel-weighted analysis
+def map2alm_pixel_weighted_raw(maps, lmax, pixel_weights):
+    """Analysis with one quadrature weight per pixel: maps [B, Npix] (RING),
+    pixel_weights [Npix] float64 (RING order) -> alm [B, nalm].  No autograd."""
+    _check_device(maps)
+    code = _DTYPES[maps.dtype]
+    maps = maps.contiguous()
+    B, n = maps.shape
+    nside = nside_of(n)
+    w = pixel_weights.to(device=maps.device, dtype=torch.float64).contiguous()
+    if w.numel() != n:
+        raise ValueError("pixel_weights needs Npix = %d entries" % n)
+    out = torch.empty((B, nalm(lmax)), dtype=_ALM_DTYPE[code], device=maps.device)
+    L = _lib.lib()
+    tab = get_tables(nside, lmax, maps.device)
+    wb = L.shtx_workspace_bytes(nside, lmax, B, code)
+    work = torch.empty(wb, dtype=torch.uint8, device=maps.device)
+    _lib.check("shtx_map2alm_pixel_weighted",
+               L.shtx_map2alm_pixel_weighted(nside, lmax, B, code, maps.data_ptr(), out.data_ptr(), w.data_ptr(),
+                                             tab.data_ptr(), work.data_ptr(), wb, _stream_ptr(maps.device)))
+    return out
+
+
+def map2alm_iter_weighted(maps, lmax, niter=3, ring_weights=None, pixel_weights=None):
+    """Refined analysis a <- a + A_w(f - S a) with the weighted analysis A_w:
+    ring_weights [2 nside] (per ring pair) and / or pixel_weights [Npix] (RING
+    order), float64; neither: equal weights.  maps [B, Npix] float64/float32."""
+    _check_device(maps)
+    squeeze = maps.dim() == 1
+    maps = (maps.unsqueeze(0) if squeeze else maps).contiguous()
+    code = _DTYPES[maps.dtype]
+    B, n = maps.shape
+    nside = nside_of(n)
+    rw = None if ring_weights is None else ring_weights.to(device=maps.device, dtype=torch.float64).contiguous()
+    pw = None if pixel_weights is None else pixel_weights.to(device=maps.device, dtype=torch.float64).contiguous()
+    if rw is not None and rw.numel() != 2 * nside:
+        raise ValueError("ring_weights needs 2*nside = %d entries" % (2 * nside))
+    if pw is not None and pw.numel() != n:
+        raise ValueError("pixel_weights needs Npix = %d entries" % n)
+    out = torch.empty((B, nalm(lmax)), dtype=_ALM_DTYPE[code], device=maps.device)
+    L = _lib.lib()
+    tab = get_tables(nside, lmax, maps.device)
+    wb = L.shtx_iter_workspace_bytes(nside, lmax, B, code)
+    if wb == 0:
+        raise ValueError("map2alm_iter_weighted needs float64 or float32 maps")
+    work = torch.empty(wb, dtype=torch.uint8, device=maps.device)
+    st = L.shtx_map2alm_iter_weighted(nside, lmax, B, code, maps.data_ptr(), out.data_ptr(), int(niter),
+                                      None if rw is None else rw.data_ptr(), None if pw is None else pw.data_ptr(),
+                                      tab.data_ptr(), work.data_ptr(), wb, _stream_ptr(maps.device))
+    _lib.check("shtx_map2alm_iter_weighted", st)
+    return out[0] if squeeze else out

@@ -1,5 +1,6 @@
-"""GPU parity of the ring-weighted analysis (through the C ABI) against the
-oracle with the same ring weights.  The weight values are arbitrary positive
+"""GPU parity of the ring- and pixel-weighted analyses and of the weighted
+refinement loop (through the C ABI) against the oracle with the same
+weights.  The weight values are arbitrary positive
 numbers (the paper's ring weights are data that does not ship here: parity of
 the weighted transform is checked, not of particular weight values)."""
 import numpy as np
@@ -46,3 +47,52 @@ def test_equal_weights_are_the_plain_analysis(shtx):
     a = shtx.map2alm_weighted_raw(x, lmax, w)
     b = shtx.map2alm_raw(x, lmax)
     assert (torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b)).item() < 1e-14
+
+
+def pair_to_ring(w_pair, nside):
+    rings = np.arange(1, 4 * nside)
+    return w_pair[np.where(rings <= 2 * nside, rings - 1, 4 * nside - 1 - rings)]
+
+
+@pytest.mark.parametrize("nside,lmax,batch,dtype", [(4, 11, 2, torch.float64), (32, 95, 3, torch.float64),
+                                                    (64, 191, 16, torch.float32), (128, 255, 2, torch.float32),
+                                                    (32, 95, 8, torch.bfloat16)])
+def test_pixel_weighted_analysis_parity(shtx, nside, lmax, batch, dtype):
+    print("\n[case] pixel weighted nside=%d lmax=%d batch=%d %s" % (nside, lmax, batch, dtype), flush=True)
+    rng = np.random.default_rng(300 + nside)
+    npx = 12 * nside * nside
+    w_pix = rng.uniform(0.5, 1.5, npx) * 4 * np.pi / npx
+    f = sht.alm2map(synth.gaussian_alm(66, batch, lmax, "lp10"), nside, lmax) + rng.standard_normal((batch, npx))
+    x = torch.tensor(f, dtype=torch.float32 if dtype == torch.bfloat16 else dtype).to(dtype)
+    ref = sht.map2alm(x.double().numpy(), lmax, nside, pixel_weights=w_pix)
+    got = shtx.map2alm_pixel_weighted_raw(x.cuda(), lmax, torch.tensor(w_pix)).cpu().numpy()
+    err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    tol = {torch.float64: 1e-12, torch.float32: 1e-5, torch.bfloat16: 2.5 * 2.0 ** -8}[dtype]
+    assert err <= tol, err
+
+
+@pytest.mark.parametrize("kind", ["equal", "ring", "pixel", "both"])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_weighted_refinement_parity(shtx, kind, dtype):
+    """a <- a + A_w(f - S a), 2 iterations, against the oracle's loop with the
+    same weights (Eq. (4) with the weight schemes of Sec. IV-A)."""
+    nside, lmax, batch = 32, 63, 3
+    print("\n[case] weighted refinement %s %s" % (kind, dtype), flush=True)
+    rng = np.random.default_rng(400)
+    npx = 12 * nside * nside
+    w_pair = rng.uniform(0.8, 1.2, 2 * nside) * 4 * np.pi / npx
+    w_pix = rng.uniform(0.8, 1.2, npx)
+    rw = w_pair if kind in ("ring", "both") else None
+    pw = w_pix * (1.0 if kind == "both" else 4 * np.pi / npx) if kind in ("pixel", "both") else None
+    f = sht.alm2map(synth.gaussian_alm(67, batch, lmax, "lp10"), nside, lmax)
+    x = torch.tensor(f, dtype=dtype)
+    okw = {}
+    if rw is not None:
+        okw["ring_weights"] = pair_to_ring(rw, nside)
+    if pw is not None:
+        okw["pixel_weights"] = pw
+    ref = sht.jacobi_map2alm(x.double().numpy(), lmax, nside, niter=2, **okw)[-1]
+    got = shtx.map2alm_iter_weighted(x.cuda(), lmax, 2, None if rw is None else torch.tensor(rw),
+                                     None if pw is None else torch.tensor(pw)).cpu().numpy()
+    err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    assert err <= TOL[dtype], err
