@@ -411,7 +411,8 @@ def run_jacobi(args):
     import paper_2510_01785_amd as shtx
     from paper_2510_01785_amd import synth
     dev = torch.device("cuda:0")
-    nside, lmax = 2048, 4095
+    nside = args.nside if args.nside != 1024 else 2048  # the refinement workload's default size
+    lmax = 2 * nside - 1
     dt = torch.float64 if args.dtype == "f64" else torch.float32
     ct = torch.complex128 if args.dtype == "f64" else torch.complex64
     print("[bench] jacobi nside=%d lmax=%d %s" % (nside, lmax, args.dtype), flush=True)
@@ -440,6 +441,25 @@ def run_jacobi(args):
     lat = np.array([x.elapsed_time(y) for x, y in evs])
     err = [float((torch.linalg.vector_norm(shtx.map2alm_iter(f, lmax, k) - a0) /
                   torch.linalg.vector_norm(a0)).item()) for k in range(4)]
+    # accuracy curve of the quadrature weight schemes (Sec. IV-A): equal
+    # weights and least-squares ring weights (host helper), per iteration:
+    # error against the input coefficients and round trip f - S(a) (RMS and
+    # max, relative to f)
+    from paper_2510_01785_amd import quadrature
+    print("[bench] jacobi accuracy curve (ring weights for nside %d)" % nside, flush=True)
+    w_pair = torch.tensor(quadrature.ring_weights_lsq(nside, lmax), dtype=torch.float64)
+    curve = {}
+    for name, rw in (("equal", None), ("ring", w_pair)):
+        rows = []
+        for k in range(5):
+            a = shtx.map2alm_iter_weighted(f, lmax, k, ring_weights=rw)
+            d = f - shtx.alm2map_raw(a, nside, lmax).to(f.dtype)
+            rows.append({"iteration": k,
+                         "alm_rel_l2": float("%.3e" % (torch.linalg.vector_norm(a - a0) /
+                                                      torch.linalg.vector_norm(a0)).item()),
+                         "round_trip_rms_rel": float("%.3e" % (d.pow(2).mean().sqrt() / f.pow(2).mean().sqrt()).item()),
+                         "round_trip_max_rel": float("%.3e" % (d.abs().max() / f.abs().max()).item())})
+        curve[name] = rows
     out = {
         "metric": "3-iteration refined map2alm, Nside=2048 lmax=4095, one map",
         "value": round(1000.0 * wall / args.steps, 3),
@@ -453,6 +473,7 @@ def run_jacobi(args):
         "dtype": args.dtype,
         "data": "synthetic",
         "rel_error_vs_input_alm_per_iteration": [float("%.3e" % e) for e in err],
+        "accuracy_curve_by_weights": curve,
         "stages_ms_per_step": stages,
         "config": {"workload": "healpix_sht_jacobi", "nside": nside, "lmax": lmax, "batch": 1, "iterations": 3,
                    "fields": "gaussian C_l=l^-2"},
