@@ -49,6 +49,8 @@ def parse():
                          "--batch coefficient sets from lmax 2 nside - 1 to 4 nside - 1; grad: forward + "
                          "spectral loss + adjoint backward at --nside, --batch, --dtype; nested: analysis of "
                          "NESTED maps, fused layout conversion vs nest2ring + map2alm")
+    ap.add_argument("--stored-lambda", action="store_true",
+                    help="with --dtype bf16: also time the forward with the resident stored-lambda table")
     ap.add_argument("--requests", type=int, default=2000)
     ap.add_argument("--rate", type=float, default=200.0)
     ap.add_argument("--budget-gib", type=float, default=48.0)
@@ -735,6 +737,35 @@ def main():
 
     value = B * args.steps / wall
     ms_per_step = 1000.0 * wall / args.steps
+    stored = None
+    if args.dtype == "bf16" and args.stored_lambda:
+        # the same forward with lambda read from the resident stored table
+        # (built once, outside the timed region) instead of the recurrence
+        print("[bench] stored-lambda table build", flush=True)
+        lam = shtx.get_lambda_table(nside, lmax, dev)
+        torch.cuda.synchronize()
+        for _ in range(args.warmup):
+            shtx.map2alm_stored_raw(maps, lmax)
+        torch.cuda.synchronize()
+        L.shtx_profile_reset()
+        L.shtx_profile_enable(1)
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            shtx.map2alm_stored_raw(maps, lmax)
+        torch.cuda.synchronize()
+        wall_s = time.perf_counter() - t1
+        L.shtx_profile_enable(0)
+        ps = _lib.profile_read()
+        a_st = shtx.map2alm_stored_raw(maps, lmax)
+        same = bool(torch.equal(a_st, shtx.map2alm_raw(maps, lmax)))
+        stored = {"maps_per_s": round(B * args.steps / wall_s, 3), "ms_per_call": round(1000.0 * wall_s / args.steps, 4),
+                  "legendre_fwd_ms": round(ps["legendre_fwd"][0] / max(ps["legendre_fwd"][1], 1), 4),
+                  "table_gb": round(lam.numel() / 1e9, 3),
+                  "table_read_gb_per_s": round(lam.numel() / (ps["legendre_fwd"][0] / max(ps["legendre_fwd"][1], 1) * 1e-3)
+                                               / 1e9, 1),
+                  "bit_identical_to_recurrence": same}
+        del lam, a_st
+        shtx.release_lambda_tables()
     # roofline of the dominant stage
     stages = {k: dict(ms_per_call=v[0] / max(v[1], 1), calls=v[1], calls_per_step=v[1] / args.steps)
               for k, v in prof.items() if v[1]}
@@ -806,6 +837,8 @@ def main():
         "roofline": roof,
         "step_roofline": step_roofline(stages, work, args.dtype, B, ms_per_step),
     }
+    if stored is not None:
+        out["stored_lambda"] = stored
     if not args.no_cpu_baseline:
         print("[bench] oracle on channel 0 of the timed step (accuracy + cpu baseline)", flush=True)
         out["accuracy_vs_oracle"], out["cpu_baseline"] = oracle_check(nside, lmax, f0, a0_gpu, g0_gpu)

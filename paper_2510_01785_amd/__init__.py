@@ -10,7 +10,8 @@ _LAZY = ("map2alm", "alm2map", "map2alm_raw", "map2alm_nested_raw", "alm2map_raw
          "alm2map_backward_raw", "map2alm_iter", "Map2Alm", "Alm2Map", "get_tables", "tables_work",
          "clear_tables",
          "workspace_bytes", "nalm", "npix", "nside_of", "nest2ring", "ring2nest", "reorder", "alm_resize",
-         "map2alm_weighted_raw", "map2alm_pixel_weighted_raw", "map2alm_iter_weighted")
+         "map2alm_weighted_raw", "map2alm_pixel_weighted_raw", "map2alm_iter_weighted",
+         "map2alm_stored_raw", "get_lambda_table", "release_lambda_tables")
 
 
 def __getattr__(name):

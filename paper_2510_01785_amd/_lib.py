@@ -14,7 +14,8 @@ EXPORTS = ("shtx_version", "shtx_status_string", "shtx_tables_bytes", "shtx_tabl
            "shtx_map2alm_iter", "shtx_profile_enable",
            "shtx_profile_reset", "shtx_profile_read", "shtx_stage_name", "shtx_nest2ring", "shtx_ring2nest",
            "shtx_alm_resize", "shtx_map2alm_weighted", "shtx_reorder", "shtx_map2alm_nested",
-           "shtx_map2alm_pixel_weighted", "shtx_map2alm_iter_weighted")
+           "shtx_map2alm_pixel_weighted", "shtx_map2alm_iter_weighted", "shtx_lambda_table_bytes",
+           "shtx_lambda_table_build", "shtx_lambda_table_release", "shtx_map2alm_stored")
 LAYOUT_RING, LAYOUT_NESTED, LAYOUT_FLAT = 0, 1, 2
 FLAT_ORIGINS = ("S", "E", "N", "W")
 STAGES = ("ring_fft_fwd", "legendre_fwd", "alm_in", "legendre_inv", "ring_fft_inv")
@@ -76,6 +77,14 @@ def lib():
     L.shtx_map2alm_pixel_weighted.restype = i
     L.shtx_map2alm_iter_weighted.argtypes = [i, i, i, i, vp, vp, i, vp, vp, vp, vp, sz, vp]
     L.shtx_map2alm_iter_weighted.restype = i
+    L.shtx_lambda_table_bytes.argtypes = [vp, ctypes.POINTER(sz), vp]
+    L.shtx_lambda_table_bytes.restype = i
+    L.shtx_lambda_table_build.argtypes = [vp, vp, sz, vp]
+    L.shtx_lambda_table_build.restype = i
+    L.shtx_lambda_table_release.argtypes = [vp]
+    L.shtx_lambda_table_release.restype = i
+    L.shtx_map2alm_stored.argtypes = [i, i, i, i, vp, vp, vp, vp, vp, sz, vp]
+    L.shtx_map2alm_stored.restype = i
     L.shtx_alm_resize.argtypes = [i, i, i, i, vp, vp, vp]
     L.shtx_alm_resize.restype = i
     L.shtx_reorder.argtypes = [i, i, i, i, i, vp, vp, vp]

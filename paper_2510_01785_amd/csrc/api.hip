@@ -18,7 +18,12 @@ template <typename TIn, typename T, typename TS>
 hipError_t launch_ring_fft_fwd(Tables, int, const TIn *, const double *, double, const double *, TS *, TS *,
                                hipStream_t, bool);
 hipError_t launch_legendre_fwd_bf16(const Tables &, int, const uint32_t *, const uint32_t *, float2 *, double, double,
-                                    int, hipStream_t);
+                                    int, hipStream_t, const uint32_t *);
+size_t lam_header_words(int nside, int nitems);
+std::vector<uint32_t> lam_tile_offsets(int nside, int lmax, int nitems, const uint8_t *ck_t, const int2 *items,
+                                       size_t *ntiles);
+hipError_t launch_lambda_table_build(const Tables &tb, uint32_t *lam, hipStream_t st);
+constexpr size_t kLamTileBytesHost = 64 * 64 * 4;  // one stored BF16 lambda tile
 template <typename TOut, typename T>
 hipError_t launch_ring_fft_inv(Tables, int, const cplx<T> *, const cplx<T> *, const TOut *, TOut *, hipStream_t);
 template <typename T>
@@ -93,6 +98,12 @@ struct Registered {
   Tables view;
 };
 std::unordered_map<const void *, Registered> g_tables;
+// stored-lambda tables: buffer -> (tables buffer, bytes it needs)
+struct LamRegistered {
+  const void *tables;
+  size_t bytes;
+};
+std::unordered_map<const void *, LamRegistered> g_lams;
 
 bool valid_geom(int nside, int lmax) {
   if (nside < 1 || (nside & (nside - 1)) != 0) return false;
@@ -216,11 +227,11 @@ template <typename TIn> bool bf16_contraction(const Tables &tb, int B) {
 template <typename TIn, typename T>
 int run_analysis(const Tables &tb, int B, const TIn *map, cplx<T> *alm, const double *wtab, double wscale,
                  double f0, double fm, void *work, hipStream_t st, int accumulate = 0, bool nested = false,
-                 const double *pixw = nullptr) {
+                 const double *pixw = nullptr, const uint32_t *lam = nullptr) {
   Work<T> w = carve<T>(work, tb, B);
   hipError_t e;
   if constexpr (std::is_same<T, float>::value) {
-    if (bf16_contraction<TIn>(tb, B)) {
+    if (lam || bf16_contraction<TIn>(tb, B)) {
       uint32_t *sa = reinterpret_cast<uint32_t *>(w.specA), *sb = reinterpret_cast<uint32_t *>(w.specB);
       {
         StageTimer t(kStFftFwd, st);
@@ -228,7 +239,7 @@ int run_analysis(const Tables &tb, int B, const TIn *map, cplx<T> *alm, const do
       }
       if (e != hipSuccess) return SHTX_ERR_HIP;
       StageTimer t(kStLegFwd, st);
-      return status_of(launch_legendre_fwd_bf16(tb, B, sa, sb, alm, f0, fm, accumulate, st));
+      return status_of(launch_legendre_fwd_bf16(tb, B, sa, sb, alm, f0, fm, accumulate, st, lam));
     }
   }
   {
@@ -497,6 +508,83 @@ int shtx_alm2map_backward(int nside, int lmax, int batch, int dtype, const void 
                                         static_cast<double2 *>(grad_alm), nullptr, 1.0, 1.0, 2.0, work, st);
   return run_analysis<float, float>(tb, batch, static_cast<const float *>(grad_map), static_cast<float2 *>(grad_alm),
                                     nullptr, 1.0, 1.0, 2.0, work, st);
+}
+
+}  // extern "C"
+
+namespace shtx {
+namespace {
+// Tile offsets of the stored-lambda table of a registered tables buffer
+// (reads the checkpoint starts back to the host: a set-up call).
+int lam_layout(const void *tables, Registered *r, std::vector<uint32_t> *off, size_t *bytes, hipStream_t st) {
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_tables.find(tables);
+    if (it == g_tables.end()) return SHTX_ERR_TABLES;
+    *r = it->second;
+  }
+  const Tables &tb = r->view;
+  if (tb.nitems == 0) return SHTX_ERR_UNSUPPORTED;
+  std::vector<uint8_t> ckt((size_t)tb.nitems * tb.npairs);
+  std::vector<int2> items(tb.nitems);
+  hipError_t e = hipStreamSynchronize(st);
+  if (e == hipSuccess) e = hipMemcpy(ckt.data(), tb.ck_t, ckt.size(), hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemcpy(items.data(), tb.ck_items, items.size() * sizeof(int2), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return SHTX_ERR_HIP;
+  size_t ntiles = 0;
+  *off = lam_tile_offsets(tb.nside, tb.lmax, tb.nitems, ckt.data(), items.data(), &ntiles);
+  *bytes = lam_header_words(tb.nside, tb.nitems) * 4 + ntiles * kLamTileBytesHost;
+  return SHTX_OK;
+}
+}  // namespace
+}  // namespace shtx
+
+extern "C" {
+
+int shtx_lambda_table_bytes(const void *tables, size_t *bytes, void *stream) {
+  if (!bytes) return SHTX_ERR_ARG;
+  Registered r;
+  std::vector<uint32_t> off;
+  return lam_layout(tables, &r, &off, bytes, static_cast<hipStream_t>(stream));
+}
+
+int shtx_lambda_table_build(const void *tables, void *lam, size_t lam_bytes, void *stream) {
+  if (!lam || (reinterpret_cast<uintptr_t>(lam) & 255)) return SHTX_ERR_ARG;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  Registered r;
+  std::vector<uint32_t> off;
+  size_t need = 0;
+  int s = lam_layout(tables, &r, &off, &need, st);
+  if (s != SHTX_OK) return s;
+  if (lam_bytes < need) return SHTX_ERR_WORKSPACE;
+  // the offsets (host memory, synchronous copy), then the tiles by the kernel
+  if (hipMemcpy(lam, off.data(), off.size() * 4, hipMemcpyHostToDevice) != hipSuccess) return SHTX_ERR_HIP;
+  if (launch_lambda_table_build(r.view, static_cast<uint32_t *>(lam), st) != hipSuccess) return SHTX_ERR_HIP;
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_lams[lam] = LamRegistered{tables, need};
+  return SHTX_OK;
+}
+
+int shtx_lambda_table_release(const void *lam) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  return g_lams.erase(lam) ? SHTX_OK : SHTX_ERR_TABLES;
+}
+
+int shtx_map2alm_stored(int nside, int lmax, int batch, int dtype, const void *map, void *alm, const void *tables,
+                        const void *lam, void *work, size_t work_bytes, void *stream) {
+  if (!lam) return SHTX_ERR_ARG;
+  Tables tb;
+  int s = check_common(nside, lmax, batch, dtype, map, alm, tables, work, work_bytes, &tb, true);
+  if (s != SHTX_OK) return s;
+  if (dtype != SHTX_BF16) return SHTX_ERR_UNSUPPORTED;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_lams.find(lam);
+    if (it == g_lams.end() || it->second.tables != tables) return SHTX_ERR_TABLES;
+  }
+  return run_analysis<bf16_t, float>(tb, batch, static_cast<const bf16_t *>(map), static_cast<float2 *>(alm), tb.rp_w,
+                                     1.0, 1.0, 1.0, work, static_cast<hipStream_t>(stream), 0, false, nullptr,
+                                     static_cast<const uint32_t *>(lam));
 }
 
 size_t shtx_iter_workspace_bytes(int nside, int lmax, int batch, int dtype) {

@@ -100,9 +100,11 @@ struct FftGeom {
 FftGeom fft_geometry(int nside, int mmax_bs, int batch, size_t csize);
 
 // Layout of the synthesis spectra g_m (Legendre output, ring FFT input):
-// per ring pair, slices of G channels (G of the ring FFT geometry), each slice
-// [m][G] contiguous -- element (p, c, m) at ((p ns + c/G) M + m) G + c%G, with
-// ns = ceil(batch/G).  A ring-FFT workgroup reads its slice as whole lines.
+// element (p, c, m) at ((p ns + c/G) M + m) G + c%G, slices of G channels.
+// Used with one slice of all channels (G = batch, ns = 1): [p][m][batch], so
+// the synthesis Legendre kernels write whole rows of channels (128-byte lines
+// at 16 FP32 channels) and the ring FFT's channel slices of one ring pair read
+// parts of the same rows close in time.
 struct SynLayout {
   int G, ns, M;
   __host__ __device__ size_t idx(int p, int c, int m) const {
@@ -111,8 +113,10 @@ struct SynLayout {
   __host__ __device__ size_t size(int npairs) const { return (size_t)npairs * ns * M * G; }
 };
 inline SynLayout syn_layout(int nside, int lmax, int mmax_bs, int batch, size_t csize) {
-  const int G = fft_geometry(nside, mmax_bs, batch, csize).G;
-  return SynLayout{G, (batch + G - 1) / G, lmax + 1};
+  (void)nside;
+  (void)mmax_bs;
+  (void)csize;
+  return SynLayout{batch, 1, lmax + 1};
 }
 
 // Readable doubles after the last coefficient (recurrence kernels load

@@ -21,9 +21,23 @@
 // 2q + 1 of a slice are its rings 2q, 2q + 1.  The spectra of a slice are
 // transposed into that K order through the same LDS tile (B operands kept in
 // registers for the whole block).
+//
+// Stored-lambda mode (the paper's precomputed Legendre tensor, Sec. III-G,
+// Eq. (28), kept resident in HBM for a hot (nside, lmax) instead of streamed
+// from the host): the same kernel, in MODE kLamBuild, writes every 64 x 128
+// BF16 lambda tile it would compute to a table in device memory (only the
+// tiles the pruned triangle executes; a per-(item, slice) offset table in front
+// of them), and in MODE kLamStored reads the tiles from that table as its A
+// operands instead of running the recurrence.  The operands and the order of
+// the products are the same, so the coefficients are bit-identical.
+#include <algorithm>
+#include <vector>
+
 #include "common.h"
 
 namespace shtx {
+
+size_t lam_header_words(int nside, int nitems);
 
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float f32x16_t __attribute__((ext_vector_type(16)));
@@ -54,9 +68,15 @@ constexpr int kBfRedRS = 32 + 1;               // row stride of the cross-wave r
 static_assert(32 * kBfRS <= kBfTileW, "spectrum staging fits the tile");
 static_assert(kBfWaves * kBlockL * kBfRedRS <= kBfWaves * kBfTileW + 512, "reduction fits the LDS");
 
+enum LamMode { kLamCompute = 0, kLamBuild = 1, kLamStored = 2 };
+constexpr int kLamTileW = kBfSub * 64;  // words of one stored tile (64 l x 64 ring pairs)
+constexpr int kLamTileBytes = kLamTileW * 4;
+
+template <int MODE>
 __global__ void __launch_bounds__(256)
     k_legendre_fwd_bf16(Tables tb, int B, const double *__restrict__ coefA, const uint32_t *__restrict__ XE,
-                        const uint32_t *__restrict__ XO, float2 *__restrict__ alm, float f0, float fm, int accum) {
+                        const uint32_t *__restrict__ XO, float2 *__restrict__ alm, float f0, float fm, int accum,
+                        const uint32_t *__restrict__ lam_off, uint32_t *__restrict__ lam_tiles) {
   const int b0 = 16 * blockIdx.y;  // channel group of this row of the grid
   __shared__ __attribute__((aligned(16))) uint32_t tile[kBfWaves * kBfTileW + 512];
   __shared__ double sA[kBlockL];
@@ -118,6 +138,12 @@ __global__ void __launch_bounds__(256)
     }
     const int tlast = __builtin_amdgcn_readfirstlane(tx);
     const int tfirst = __builtin_amdgcn_readfirstlane(tn);
+    // stored tiles of this (item, slice): hb 0 (if active) then hb 1
+    uint32_t toff = 0;
+    if constexpr (MODE != kLamCompute) {
+      const int nslices = (Rp + kBfSlice - 1) / kBfSlice;
+      toff = __builtin_amdgcn_readfirstlane(lam_off[(size_t)item * nslices + q0 / kBfSlice]);
+    }
 
     // spectra of the slice -> B operands: staging [col][ring pair] words
     // (row stride kBfRS), each word the two rings of one pair; a lane loads
@@ -126,6 +152,7 @@ __global__ void __launch_bounds__(256)
     u32x4_t xop[2][8];
 #pragma unroll
     for (int par = 0; par < 2; ++par) {
+      if constexpr (MODE == kLamBuild) break;  // the table build needs no spectra
       const uint32_t *X = par ? XO : XE;
       uint32_t pa[2][2][4], pb[2][2][4];
 #pragma unroll
@@ -183,8 +210,10 @@ __global__ void __launch_bounds__(256)
       // lmax (output rows that are never stored)
       if (hb == 0 && tfirst >= kBfSub) continue;
       if (hb == 1 && l0 + kBfSub > L) continue;
+      uint32_t *gt = lam_tiles + (size_t)(toff + (hb == 1 && tfirst < kBfSub ? 1u : 0u)) * kLamTileW;
 #pragma unroll 1
       for (int t8 = 0; t8 < kBfSub / 8; ++t8) {
+        if constexpr (MODE == kLamStored) break;  // lambda comes from the table
         const int tb8 = hb * kBfSub + t8 * 8;
         int aaddr = tb8;
         asm volatile("" : "+v"(aaddr));
@@ -196,7 +225,9 @@ __global__ void __launch_bounds__(256)
           Ac[2 * u] = a2.x;
           Ac[2 * u + 1] = a2.y;
         }
-        uint32_t *trow = tw + (t8 * 8) * kBfRS + j;
+        // the tile row of l = tb8 + u: this wave's LDS tile, or the table
+        uint32_t *trow = MODE == kLamBuild ? gt + (t8 * 8) * 64 + j : tw + (t8 * 8) * kBfRS + j;
+        const int rs = MODE == kLamBuild ? 64 : kBfRS;
         if (tb8 <= tlast) {  // uniform: some ring starts in this group
 #pragma unroll
           for (int u = 0; u < 8; ++u) {
@@ -214,7 +245,7 @@ __global__ void __launch_bounds__(256)
               pb_ = cb;
               cb = xb;
             }
-            trow[u * kBfRS] = pack_bf16x2(f64_to_f32(ca), f64_to_f32(cb));
+            trow[u * rs] = pack_bf16x2(f64_to_f32(ca), f64_to_f32(cb));
           }
         } else {
 #pragma unroll
@@ -225,19 +256,23 @@ __global__ void __launch_bounds__(256)
             ca = xa;
             pb_ = cb;
             cb = xb;
-            trow[u * kBfRS] = pack_bf16x2(f64_to_f32(ca), f64_to_f32(cb));
+            trow[u * rs] = pack_bf16x2(f64_to_f32(ca), f64_to_f32(cb));
           }
         }
       }
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      if constexpr (MODE == kLamBuild) continue;
       // contraction: even rows l0 + hb*64 + 2i, odd rows + 1; K = 8 steps of
-      // 16 rings (8 ring pairs = 4 words per lane)
+      // 16 rings (8 ring pairs = 4 words per lane); A from the LDS tile, or
+      // (stored mode) from the table
+      const uint32_t *at = MODE == kLamStored ? gt : tw;
+      const int ars = MODE == kLamStored ? 64 : kBfRS;
 #pragma unroll
       for (int k = 0; k < 8; ++k) {
-        const u32x4_t ae = *reinterpret_cast<const u32x4_t *>(tw + (2 * col) * kBfRS + 8 * k + 4 * h);
-        const u32x4_t ao = *reinterpret_cast<const u32x4_t *>(tw + (2 * col + 1) * kBfRS + 8 * k + 4 * h);
+        const u32x4_t ae = *reinterpret_cast<const u32x4_t *>(at + (2 * col) * ars + 8 * k + 4 * h);
+        const u32x4_t ao = *reinterpret_cast<const u32x4_t *>(at + (2 * col + 1) * ars + 8 * k + 4 * h);
         acc[hb * 2 + 0] = mfma_bf16(ae, xop[0][k], acc[hb * 2 + 0]);
         acc[hb * 2 + 1] = mfma_bf16(ao, xop[1][k], acc[hb * 2 + 1]);
       }
@@ -246,6 +281,7 @@ __global__ void __launch_bounds__(256)
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
   }
+  if constexpr (MODE == kLamBuild) return;
   // sum the four waves' partial tiles, red[w][l - l0][col], and write the
   // caller's layout alm[b][idx(l, m)] = f_m c_lm a (Im = 0 for m = 0), or add
   __syncthreads();
@@ -287,20 +323,65 @@ __global__ void __launch_bounds__(256)
   }
 }
 
-hipError_t launch_legendre_fwd_bf16(const Tables &tb, int B, const uint32_t *XE, const uint32_t *XO, float2 *alm,
-                                    double f0, double fm, int accum, hipStream_t st) {
-  if (tb.nitems == 0) return hipErrorInvalidValue;
+static int longest_xcd_items(int L) {
   int longest = 0;
-  {
-    const int L = tb.lmax;
-    for (int xg = 0; xg < 8; ++xg) {
-      int c = 0;
-      for (int m = xg; m <= L; m += 8) c += (L - m + kBlockL) / kBlockL;
-      longest = c > longest ? c : longest;
+  for (int xg = 0; xg < 8; ++xg) {
+    int c = 0;
+    for (int m = xg; m <= L; m += 8) c += (L - m + kBlockL) / kBlockL;
+    longest = c > longest ? c : longest;
+  }
+  return longest;
+}
+
+hipError_t launch_legendre_fwd_bf16(const Tables &tb, int B, const uint32_t *XE, const uint32_t *XO, float2 *alm,
+                                    double f0, double fm, int accum, hipStream_t st, const uint32_t *lam) {
+  if (tb.nitems == 0) return hipErrorInvalidValue;
+  const dim3 grid(8 * longest_xcd_items(tb.lmax), (B + 15) / 16);
+  if (lam) {
+    const uint32_t *tiles = lam + lam_header_words(tb.nside, tb.nitems);
+    hipLaunchKernelGGL(k_legendre_fwd_bf16<kLamStored>, grid, dim3(256), 0, st, tb, B, tb.coefA, XE, XO, alm,
+                       (float)f0, (float)fm, accum, lam, const_cast<uint32_t *>(tiles));
+  } else {
+    hipLaunchKernelGGL(k_legendre_fwd_bf16<kLamCompute>, grid, dim3(256), 0, st, tb, B, tb.coefA, XE, XO, alm,
+                       (float)f0, (float)fm, accum, nullptr, nullptr);
+  }
+  return hipGetLastError();
+}
+
+// The stored-lambda table: per (item, 128-ring slice) the index of its first
+// tile (header, lam_header_words words), then the tiles.  A slice has a tile
+// for each of its active half blocks, by the rule the kernel applies (any
+// ring active in the block; the first half block if some ring starts in it,
+// the second if it holds l <= lmax).
+size_t lam_header_words(int nside, int nitems) {
+  const size_t ns = (2 * (size_t)nside + kBfSlice - 1) / kBfSlice;
+  return align_up((size_t)nitems * ns, 1024);
+}
+
+std::vector<uint32_t> lam_tile_offsets(int nside, int lmax, int nitems, const uint8_t *ck_t, const int2 *items,
+                                       size_t *ntiles) {
+  const int Rp = 2 * nside, ns = (Rp + kBfSlice - 1) / kBfSlice;
+  std::vector<uint32_t> off((size_t)nitems * ns);
+  size_t run = 0;
+  for (int it = 0; it < nitems; ++it) {
+    const int l0 = items[it].y;
+    for (int s = 0; s < ns; ++s) {
+      int tmin = kBlockL;
+      for (int q = s * kBfSlice; q < std::min(Rp, (s + 1) * kBfSlice); ++q)
+        tmin = std::min(tmin, (int)ck_t[(size_t)it * Rp + q]);
+      off[(size_t)it * ns + s] = (uint32_t)run;
+      if (tmin < kBlockL) run += (size_t)(tmin < kBfSub) + (size_t)(l0 + kBfSub <= lmax);
     }
   }
-  hipLaunchKernelGGL(k_legendre_fwd_bf16, dim3(8 * longest, (B + 15) / 16), dim3(256), 0, st, tb, B, tb.coefA, XE,
-                     XO, alm, (float)f0, (float)fm, accum);
+  *ntiles = run;
+  return off;
+}
+
+hipError_t launch_lambda_table_build(const Tables &tb, uint32_t *lam, hipStream_t st) {
+  if (tb.nitems == 0) return hipErrorInvalidValue;
+  const dim3 grid(8 * longest_xcd_items(tb.lmax), 1);
+  hipLaunchKernelGGL(k_legendre_fwd_bf16<kLamBuild>, grid, dim3(256), 0, st, tb, 16, tb.coefA, nullptr, nullptr,
+                     nullptr, 1.f, 1.f, 0, lam, lam + lam_header_words(tb.nside, tb.nitems));
   return hipGetLastError();
 }
 

@@ -263,8 +263,9 @@ __global__ void __launch_bounds__(256)
 // (L1/L2), one group ahead: no LDS, no barriers, and every wave starts at its
 // own rings' first non-negligible l.  Workgroups are dealt so that all chunks
 // of eight consecutive m run on one XCD (consecutive workgroups go to
-// consecutive XCDs): they share the a_m slabs in L2 and together fill whole
-// lines of the slice-major synthesis spectra.
+// consecutive XCDs): they share the a_m slabs in L2.  A wave writes, per ring
+// pair, whole [m][batch] rows of the synthesis spectra (32 consecutive floats
+// per ring: one 128-byte line at 16 channels).
 constexpr int kInvRings = 64;
 
 // (lanes 0-31 of x | lanes 0-31 of y) and (lanes 32-63 of x | lanes 32-63 of y)

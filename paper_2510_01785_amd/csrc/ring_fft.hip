@@ -902,10 +902,11 @@ __global__ void __launch_bounds__(NT, sizeof(T) == 4 ? 4 : 1)
   int tid = threadIdx.x;
   // c_m = g_m exp(+i m phi0), mm = m mod 2n
   const RingPhase<T> rph = ring_phase<T>(tb, n, num);
-  auto phased = [&](const C *src, int m, int mm) { return cmul(src[(size_t)m * G], rph.plus(mm)); };
-  // this workgroup's channel slice [m][G] of the synthesis spectra
-  const int ns = (B + G - 1) / G;
-  const size_t sbase = ((size_t)p * ns + bg0 / G) * M * G;
+  // synthesis spectra [p][m][B]: this workgroup reads channels [bg0, bg1) of
+  // each m row (the other channel slices of the row are read by the
+  // workgroups of the same ring pair, dealt to the same XCD at the same time)
+  auto phased = [&](const C *src, int m, int mm) { return cmul(src[(size_t)m * B], rph.plus(mm)); };
+  const size_t sbase = (size_t)p * M * B + bg0;
   // Fold onto k = m mod n (positive frequencies) and k = -m mod n (negative,
   // conj) for channel c of the slice at gn / gs: the first term of each sum is
   // loaded by fold_load (so that several items can have their loads in
@@ -915,12 +916,12 @@ __global__ void __launch_bounds__(NT, sizeof(T) == 4 ? 4 : 1)
     const int m1 = k, m2 = (k == 0) ? n : n - k;
     pn = ps = qn = qs = cmk<C>(0, 0);
     if (m1 < M) {
-      pn = gn[(size_t)m1 * G + c];
-      if (!equator) ps = gs[(size_t)m1 * G + c];
+      pn = gn[(size_t)m1 * B + c];
+      if (!equator) ps = gs[(size_t)m1 * B + c];
     }
     if (m2 < M) {
-      qn = gn[(size_t)m2 * G + c];
-      if (!equator) qs = gs[(size_t)m2 * G + c];
+      qn = gn[(size_t)m2 * B + c];
+      if (!equator) qs = gs[(size_t)m2 * B + c];
     }
   };
   // C_N, C_S at k (the sums over the aliases m = +-k mod n of g_m exp(i m phi0),

@@ -351,3 +351,61 @@ def map2alm_iter_weighted(maps, lmax, niter=3, ring_weights=None, pixel_weights=
                                       tab.data_ptr(), work.data_ptr(), wb, _stream_ptr(maps.device))
     _lib.check("shtx_map2alm_iter_weighted", st)
     return out[0] if squeeze else out
+
+
+# ---------------------------------------------------------- stored lambda
+_lams = {}
+
+
+def get_lambda_table(nside, lmax, device):
+    """Resident stored-lambda table (uint8 tensor) for (nside, lmax) on
+    `device`, built once: the BF16 Legendre operands of the BF16 matrix-core
+    analysis (tiles of the pruned triangle)."""
+    import ctypes
+    device = torch.device(device)
+    key = (nside, lmax, device.index if device.index is not None else torch.cuda.current_device())
+    with _tables_lock:
+        t = _lams.get(key)
+        if t is not None:
+            return t
+    tab = get_tables(nside, lmax, device)
+    L = _lib.lib()
+    nb = ctypes.c_size_t(0)
+    _lib.check("shtx_lambda_table_bytes", L.shtx_lambda_table_bytes(tab.data_ptr(), ctypes.byref(nb),
+                                                                     _stream_ptr(device)))
+    t = torch.empty(nb.value, dtype=torch.uint8, device=device)
+    _lib.check("shtx_lambda_table_build", L.shtx_lambda_table_build(tab.data_ptr(), t.data_ptr(), nb.value,
+                                                                     _stream_ptr(device)))
+    with _tables_lock:
+        _lams[key] = t
+    return t
+
+
+def release_lambda_tables():
+    with _tables_lock:
+        L = _lib.lib()
+        for t in _lams.values():
+            L.shtx_lambda_table_release(t.data_ptr())
+        _lams.clear()
+
+
+def map2alm_stored_raw(maps, lmax):
+    """BF16 maps [B, Npix] -> alm [B, nalm] complex64 through the BF16
+    matrix-core analysis with lambda read from the resident stored table
+    (built on first use).  No autograd."""
+    _check_device(maps)
+    if maps.dtype != torch.bfloat16:
+        raise ValueError("the stored-lambda analysis takes bfloat16 maps")
+    maps = maps.contiguous()
+    B, n = maps.shape
+    nside = nside_of(n)
+    lam = get_lambda_table(nside, lmax, maps.device)
+    L = _lib.lib()
+    tab = get_tables(nside, lmax, maps.device)
+    wb = L.shtx_workspace_bytes(nside, lmax, B, _lib.BF16)
+    work = torch.empty(wb, dtype=torch.uint8, device=maps.device)
+    out = torch.empty((B, nalm(lmax)), dtype=torch.complex64, device=maps.device)
+    _lib.check("shtx_map2alm_stored",
+               L.shtx_map2alm_stored(nside, lmax, B, _lib.BF16, maps.data_ptr(), out.data_ptr(), tab.data_ptr(),
+                                     lam.data_ptr(), work.data_ptr(), wb, _stream_ptr(maps.device)))
+    return out

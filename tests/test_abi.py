@@ -36,11 +36,10 @@ def nalm(l):
     return (l + 1) * (l + 2) // 2
 
 
-# (nside, lmax, batch, dtype, spectrum channels: batch rounded up to the ring
-# FFT's channel slices -- 2 channels of 4096-point rings at nside 1024 FP32)
+# (nside, lmax, batch, dtype, spectrum channels: the batch)
 @pytest.mark.parametrize("nside,lmax,batch,dtype,bspec", [(32, 95, 1, 0, 1), (1024, 2047, 16, 1, 16),
                                                            (1024, 2047, 16, 2, 16), (2048, 4095, 1, 0, 1),
-                                                           (1, 0, 3, 1, 3), (1024, 2047, 5, 1, 6)])
+                                                           (1, 0, 3, 1, 3), (1024, 2047, 5, 1, 5)])
 def test_workspace_closed_form(nside, lmax, batch, dtype, bspec):
     cs = 16 if dtype == 0 else 8
     up = lambda x: (x + 255) // 256 * 256

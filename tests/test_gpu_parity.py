@@ -309,3 +309,25 @@ def test_jacobi_iteration_parity(shtx, nside, lmax, batch, dtype, niter):
     ref = sht.jacobi_map2alm(x.double().cpu().numpy(), lmax, nside, niter=niter)[-1]
     got = shtx.map2alm_iter(x, lmax, niter).cpu().numpy()
     assert rel_l2(got, ref) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("nside,lmax,batch", [(16, 47, 8), (64, 191, 16), (128, 383, 16), (256, 511, 20),
+                                              (32, 95, 3)])
+def test_stored_lambda_analysis(shtx, nside, lmax, batch, monkeypatch):
+    """The stored-lambda analysis (BF16 Legendre tiles built once into a
+    resident table, Sec. III-G, then read instead of recomputed): bit-identical
+    to the BF16 matrix-core analysis that computes them (from 5 channels; below
+    that map2alm takes the FP32 vector-ALU path, so the comparison is with the
+    oracle at the BF16 bar), and within the BF16 bar of the oracle."""
+    announce("stored lambda nside=%d lmax=%d B=%d" % (nside, lmax, batch))
+    for k in ("SHTX_BF16_CONTRACT", "SHTX_FORCE_VALU", "SHTX_MFMA_MIN_BATCH"):
+        monkeypatch.delenv(k, raising=False)
+    f = synth.white_map(6300 + batch, batch, geometry.npix(nside))
+    x = torch.tensor(f, dtype=torch.float32, device="cuda").to(torch.bfloat16)
+    got = shtx.map2alm_stored_raw(x, lmax)
+    if batch >= 5:
+        assert torch.equal(got, shtx.map2alm_raw(x, lmax))
+    ref = sht.map2alm(x.float().double().cpu().numpy(), lmax, nside)
+    err = rel_l2(got.cpu().numpy(), ref)
+    print("[stored lambda] nside=%d lmax=%d B=%d rel l2 vs oracle %.3e" % (nside, lmax, batch, err), flush=True)
+    assert err <= BF16_CONTRACT_TOL
