@@ -3,12 +3,16 @@ on one GPU, with admission against an HBM budget and overlap on streams.
 
 A request is one map2alm or alm2map call on a batch of channels already
 resident in device memory.  `Server.submit` queues it and returns a Future.
-An admission thread takes queued requests in arrival order; a request is
-started when a stream slot is free and its device memory (output, workspace
-and, for a new (nside, lmax), the resident tables) fits in what is left of the
-budget.  It then runs on that slot's stream and an event marks its end.  A
-completion thread resolves the futures in completion order, then returns the
-memory and the slot, which admits the next requests.
+An admission thread scans the queue in arrival order and starts the first
+request whose device memory (output and workspace, plus the resident tables
+of an (nside, lmax) not seen before) fits in what is left of the budget, when
+a stream slot is free: a large request at the head that does not fit yet does
+not hold back smaller ones behind it, but once it has been passed over
+`max_skips` times nothing behind it is admitted until it has started (no
+starvation).  A request runs on its slot's stream and an event marks its end.
+A completion thread resolves the futures in completion order, then returns
+the request's transient memory and its slot, which admits the next requests.
+Tables stay resident once built, so their bytes stay charged to the budget.
 
 * A request whose memory alone exceeds the budget is rejected at submit
   (its future fails with `AdmissionError`); nothing is allocated.
@@ -17,12 +21,13 @@ memory and the slot, which admits the next requests.
 * Per request the loop records arrival, admit and done times; `stats()`
   reports p50/p99 latency, maps/s, memory in use and queue depth.
 * The budget covers what the loop allocates while a request runs (output,
-  workspace, tables of a new (nside, lmax)); a finished request's output
+  workspace) and the tables it keeps resident; a finished request's output
   belongs to its future, i.e. to the caller.
 
 The scheduling core (`Scheduler`) is independent of the device: it drives an
-executor with `need(req)`, `launch(req, slot)`, `done(handle)` and
-`finish(handle)`.  `Server` pairs it with the GPU executor built on the C-ABI
+executor with `need(req)` (bytes held while the request runs, or a pair
+(those bytes, bytes that stay resident once it has run)), `launch(req,
+slot)`, `done(handle)` and `finish(handle)`.  `Server` pairs it with the GPU executor built on the C-ABI
 binding (`ops`); tests drive it with a host executor.
 """
 import collections
@@ -49,7 +54,8 @@ class Request:
     t_arrival: float = 0.0
     t_admit: float = 0.0
     t_done: float = 0.0
-    need: int = 0
+    need: int = 0           # bytes returned to the budget when the request ends
+    skipped: int = 0        # times a later request was admitted ahead of this one
     future: concurrent.futures.Future = field(default_factory=concurrent.futures.Future)
 
     @property
@@ -66,14 +72,25 @@ class Done:
     need: int
 
 
-class Scheduler:
-    """FIFO admission under a memory budget and a slot count."""
+def _split_need(n):
+    """(transient, resident) bytes from an executor's need()."""
+    if isinstance(n, tuple):
+        return int(n[0]), int(n[1])
+    return int(n), 0
 
-    def __init__(self, executor, budget_bytes, slots, poll_s=2e-4):
+
+class Scheduler:
+    """Admission under a memory budget and a slot count: arrival order, with
+    requests that fit admitted ahead of a blocked head at most `max_skips`
+    times (default: twice the slot count)."""
+
+    def __init__(self, executor, budget_bytes, slots, poll_s=2e-4, max_skips=None):
         self.ex = executor
         self.budget = int(budget_bytes)
         self.slots = int(slots)
         self.poll_s = poll_s
+        self.max_skips = 2 * self.slots if max_skips is None else int(max_skips)
+        self.resident = 0            # bytes that stay charged (tables kept resident)
         self._cv = threading.Condition()
         self._queue = collections.deque()
         self._free_slots = list(range(self.slots))
@@ -91,10 +108,11 @@ class Scheduler:
     # ---------------------------------------------------------------- API
     def submit(self, req):
         req.t_arrival = time.perf_counter()
-        req.need = int(self.ex.need(req))
-        if req.need > self.budget:
+        t, r = _split_need(self.ex.need(req))
+        if t + r > self.budget - self.resident:
             req.future.set_exception(AdmissionError(
-                "request needs %d bytes, budget is %d" % (req.need, self.budget)))
+                "request needs %d bytes, budget is %d (%d held by resident tables)"
+                % (t + r, self.budget, self.resident)))
             return req.future
         with self._cv:
             if self._closed:
@@ -122,6 +140,20 @@ class Scheduler:
             t.join()
 
     # ----------------------------------------------------------- threads
+    def _pick_locked(self):
+        """Index of the request to admit now and its (transient, resident)
+        bytes, or None: the first queued request that fits, scanning no
+        further than a request that has been passed over max_skips times."""
+        if not self._free_slots:
+            return None
+        for i, r in enumerate(self._queue):
+            t, res = _split_need(self.ex.need(r))
+            if self.in_use + t + res <= self.budget:
+                return i, t, res
+            if r.skipped >= self.max_skips:
+                return None
+        return None
+
     def _admit_loop(self):
         while True:
             with self._cv:
@@ -129,23 +161,32 @@ class Scheduler:
                     if self._closed and not self._queue:
                         return
                     self._drop_dead_locked()
-                    if self._queue and self._free_slots and \
-                            self.in_use + self._queue[0].need <= self.budget:
+                    pick = self._pick_locked()
+                    if pick is not None:
                         break
                     self._cv.wait(0.05)
-                req = self._queue.popleft()
+                i, t, res = pick
+                req = self._queue[i]
+                del self._queue[i]
+                for j in range(i):
+                    self._queue[j].skipped += 1
                 if not req.future.set_running_or_notify_cancel():
                     continue
                 slot = self._free_slots.pop(0)
-                self.in_use += req.need
+                req.need = t
+                self.in_use += t + res
+                self.resident += res
                 self.peak_in_use = max(self.peak_in_use, self.in_use)
                 req.t_admit = time.perf_counter()
                 self._launching += 1
             try:
                 handle = self.ex.launch(req, slot)
             except Exception as e:  # launch failed: release and report
+                # resident bytes go back too if the tables were not kept
+                lost = res if _split_need(self.ex.need(req))[1] > 0 else 0
                 with self._cv:
-                    self.in_use -= req.need
+                    self.in_use -= req.need + lost
+                    self.resident -= lost
                     self._free_slots.append(slot)
                     self._launching -= 1
                     self._cv.notify_all()
@@ -206,8 +247,10 @@ class Scheduler:
             fin = list(self.finished)
             depth = len(self._queue)
             in_use = self.in_use
+            resident = self.resident
         if not fin:
-            return dict(requests=0, queue_depth=depth, in_use_bytes=in_use, peak_in_use_bytes=self.peak_in_use)
+            return dict(requests=0, queue_depth=depth, in_use_bytes=in_use, resident_bytes=resident,
+                        peak_in_use_bytes=self.peak_in_use)
         lat = np.array([r.t_done - r.t_arrival for r in fin]) * 1e3
         wait = np.array([r.t_admit - r.t_arrival for r in fin]) * 1e3
         t0 = min(r.t_arrival for r in fin) if t0 is None else t0
@@ -217,8 +260,8 @@ class Scheduler:
                     p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
                     queue_wait_p50_ms=float(np.percentile(wait, 50)),
                     queue_wait_p99_ms=float(np.percentile(wait, 99)),
-                    queue_depth=depth, in_use_bytes=in_use, peak_in_use_bytes=self.peak_in_use,
-                    budget_bytes=self.budget)
+                    queue_depth=depth, in_use_bytes=in_use, resident_bytes=resident,
+                    peak_in_use_bytes=self.peak_in_use, budget_bytes=self.budget)
 
 
 class GpuExecutor:
@@ -230,8 +273,9 @@ class GpuExecutor:
         self.torch, self.ops = torch, ops
         self.device = torch.device(device)
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(slots)]  # default priority
+        self.table_stream = torch.cuda.Stream(device=self.device)  # default priority
         self._tables_lock = threading.Lock()
-        self._tables = set()
+        self._tables = {}  # (nside, lmax) -> event recorded after the tables' build
 
     def _out_bytes(self, req):
         B = req.batch
@@ -252,17 +296,26 @@ class GpuExecutor:
             raise ValueError("unknown direction %r" % req.direction)
         L = _lib.lib()
         ws = L.shtx_workspace_bytes(req.nside, req.lmax, req.batch, code)
-        tab = 0 if (req.nside, req.lmax) in self._tables else L.shtx_tables_bytes(req.nside, req.lmax)
-        return self._out_bytes(req) + ws + tab
+        with self._tables_lock:
+            known = (req.nside, req.lmax) in self._tables
+        tab = 0 if known else L.shtx_tables_bytes(req.nside, req.lmax)
+        return self._out_bytes(req) + ws, tab
 
     def launch(self, req, slot):
         torch, ops = self.torch, self.ops
+        key = (req.nside, req.lmax)
         with self._tables_lock:
-            if (req.nside, req.lmax) not in self._tables:
-                ops.get_tables(req.nside, req.lmax, self.device)
-                torch.cuda.synchronize(self.device)  # tables ready for every stream
-                self._tables.add((req.nside, req.lmax))
+            ev_tab = self._tables.get(key)
+            if ev_tab is None:
+                # built on the table stream; requests wait for that event on
+                # their own streams (no device-wide synchronisation)
+                with torch.cuda.stream(self.table_stream):
+                    ops.get_tables(req.nside, req.lmax, self.device)
+                    ev_tab = torch.cuda.Event()
+                    ev_tab.record(self.table_stream)
+                self._tables[key] = ev_tab
         st = self.streams[slot]
+        st.wait_event(ev_tab)
         st.wait_stream(torch.cuda.current_stream(self.device))  # inputs written before submit
         with torch.cuda.stream(st):
             if req.direction == "map2alm":

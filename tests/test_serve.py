@@ -51,8 +51,9 @@ def make(need, tag, batch=1, timeout=None):
 
 
 def test_budget_never_exceeded_and_fifo():
+    """max_skips=0: strict arrival order under the budget and slot count."""
     ex = HostExecutor(0.005)
-    s = Scheduler(ex, budget_bytes=100, slots=4)
+    s = Scheduler(ex, budget_bytes=100, slots=4, max_skips=0)
     reqs = [make(30 + (i % 3) * 20, i) for i in range(40)]
     futs = [s.submit(r) for r in reqs]
     for f in futs:
@@ -64,6 +65,59 @@ def test_budget_never_exceeded_and_fifo():
     assert ex.max_live <= 4
     assert [t for t, _ in ex.launched] == list(range(40))  # admitted in arrival order
     assert s.in_use == 0
+
+
+def test_small_requests_pass_a_blocked_head_without_starving_it():
+    """A head request that does not fit yet lets later ones that fit start,
+    at most max_skips times; then it starts before anything behind it."""
+    ex = HostExecutor(0.03)
+    s = Scheduler(ex, budget_bytes=100, slots=8, max_skips=3)
+    first = s.submit(make(60, "first"))
+    time.sleep(0.005)
+    big = s.submit(make(80, "big"))            # blocked while "first" runs
+    small = [s.submit(make(10, "s%d" % i)) for i in range(6)]
+    for f in [first, big] + small:
+        f.result(timeout=10)
+    s.close()
+    order = [t for t, _ in ex.launched]
+    assert order[0] == "first"
+    # exactly max_skips small requests went ahead of the blocked head, the
+    # rest waited behind it
+    assert order.index("big") == 1 + 3
+    assert s.peak_in_use <= 100 and s.in_use == 0
+
+
+class TableExecutor(HostExecutor):
+    """need = (transient, resident): 'tables' of a new key stay resident."""
+
+    def __init__(self, dur=0.005):
+        super().__init__(dur)
+        self.keys = set()
+
+    def need(self, req):
+        return (req.nside, 0 if req.lmax in self.keys else 25)
+
+    def launch(self, req, slot):
+        self.keys.add(req.lmax)
+        return super().launch(req, slot)
+
+
+def test_resident_tables_stay_charged():
+    ex = TableExecutor()
+    s = Scheduler(ex, budget_bytes=100, slots=2)
+    futs = [s.submit(make(10, k % 3)) for k in range(9)]
+    for f in futs:
+        f.result(timeout=10)
+    st = s.stats()
+    s.close()
+    assert st["resident_bytes"] == 3 * 25 and s.in_use == 3 * 25
+    assert s.peak_in_use <= 100
+    # a request that no longer fits beside the resident tables is rejected
+    s2 = Scheduler(ex, budget_bytes=100, slots=2)
+    s2.resident = s2.in_use = 80
+    with pytest.raises(AdmissionError):
+        s2.submit(make(30, 0)).result(timeout=1)
+    s2.close()
 
 
 def test_over_budget_rejected_without_launch():
@@ -109,7 +163,7 @@ def test_stats_well_formed():
     s.close()
     assert st["requests"] == 30 and st["maps"] > 0
     assert 0 < st["p50_ms"] <= st["p99_ms"]
-    assert st["queue_depth"] == 0 and st["in_use_bytes"] == 0
+    assert st["queue_depth"] == 0 and st["in_use_bytes"] == 0 and st["resident_bytes"] == 0
     assert st["peak_in_use_bytes"] <= 1000 and st["maps_per_s"] > 0
 
 
