@@ -6,7 +6,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libshtx.so")
 
 F64, F32, BF16 = 0, 1, 2
-OK, ERR_ARG, ERR_UNSUPPORTED, ERR_WORKSPACE, ERR_HIP, ERR_TABLES = range(6)
+OK, ERR_ARG, ERR_UNSUPPORTED, ERR_WORKSPACE, ERR_HIP, ERR_TABLES, ERR_SCRATCH = range(7)
 
 EXPORTS = ("shtx_version", "shtx_status_string", "shtx_tables_bytes", "shtx_tables_build",
            "shtx_tables_release", "shtx_tables_work", "shtx_workspace_bytes", "shtx_map2alm", "shtx_alm2map",
@@ -15,7 +15,8 @@ EXPORTS = ("shtx_version", "shtx_status_string", "shtx_tables_bytes", "shtx_tabl
            "shtx_profile_reset", "shtx_profile_read", "shtx_stage_name", "shtx_nest2ring", "shtx_ring2nest",
            "shtx_alm_resize", "shtx_map2alm_weighted", "shtx_reorder", "shtx_map2alm_nested",
            "shtx_map2alm_pixel_weighted", "shtx_map2alm_iter_weighted", "shtx_lambda_table_bytes",
-           "shtx_lambda_table_build", "shtx_lambda_table_release", "shtx_map2alm_stored")
+           "shtx_lambda_table_build", "shtx_lambda_table_release", "shtx_map2alm_stored",
+           "shtx_noalloc_scratch_bytes", "shtx_map2alm_noalloc")
 LAYOUT_RING, LAYOUT_NESTED, LAYOUT_FLAT = 0, 1, 2
 FLAT_ORIGINS = ("S", "E", "N", "W")
 STAGES = ("ring_fft_fwd", "legendre_fwd", "alm_in", "legendre_inv", "ring_fft_inv")
@@ -85,6 +86,10 @@ def lib():
     L.shtx_lambda_table_release.restype = i
     L.shtx_map2alm_stored.argtypes = [i, i, i, i, vp, vp, vp, vp, vp, sz, vp]
     L.shtx_map2alm_stored.restype = i
+    L.shtx_noalloc_scratch_bytes.argtypes = []
+    L.shtx_noalloc_scratch_bytes.restype = sz
+    L.shtx_map2alm_noalloc.argtypes = [i, i, i, i, vp, vp, vp, vp]
+    L.shtx_map2alm_noalloc.restype = i
     L.shtx_alm_resize.argtypes = [i, i, i, i, vp, vp, vp]
     L.shtx_alm_resize.restype = i
     L.shtx_reorder.argtypes = [i, i, i, i, i, vp, vp, vp]

@@ -162,6 +162,41 @@ template <typename T> Work<T> carve(void *work, const Tables &tb, int batch) {
 
 constexpr int kMaxIter = 64;  // refinement iterations accepted by shtx_map2alm_iter
 
+// ---------------------------------------------- allocation-free analysis
+// Fixed device scratch of shtx_map2alm_noalloc: the two analysis spectrum
+// buffers live here instead of in a caller workspace.  One copy per device,
+// held until the process ends; calls on one device share it.  Host code
+// never uses the array's name as an address: the device address of each
+// device's copy is looked up once (hipGetSymbolAddress, that device current)
+// and kept in g_scratch_ptr.
+constexpr size_t kScratchBytes = (size_t)SHTX_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};  // device address of `scratch` per device
+
+// Device address of the current device's scratch array (looked up on the
+// first call on that device); nullptr and *status set on failure.
+void *scratch_ptr(int *status) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+    *status = SHTX_ERR_HIP;
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+      *status = SHTX_ERR_HIP;
+      return nullptr;
+    }
+    g_scratch_ptr[dev] = p;
+  }
+  *status = SHTX_OK;
+  return g_scratch_ptr[dev];
+}
+
 int status_of(hipError_t e) { return e == hipSuccess ? SHTX_OK : SHTX_ERR_HIP; }
 
 // Matrix-core Legendre kernels serve FP32 contraction from mfma_min_batch()
@@ -321,6 +356,7 @@ const char *shtx_status_string(int status) {
     case SHTX_ERR_WORKSPACE: return "workspace too small";
     case SHTX_ERR_HIP: return "HIP runtime error";
     case SHTX_ERR_TABLES: return "tables not built for this (nside, lmax)";
+    case SHTX_ERR_SCRATCH: return "request needs more than the fixed scratch of the allocation-free entry point";
     default: return "unknown status";
   }
 }
@@ -386,6 +422,44 @@ int shtx_map2alm(int nside, int lmax, int batch, int dtype, const void *map, voi
                  void *work, size_t work_bytes, void *stream) {
   Tables tb;
   int s = check_common(nside, lmax, batch, dtype, map, alm, tables, work, work_bytes, &tb, true);
+  if (s != SHTX_OK) return s;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  switch (dtype) {
+    case SHTX_F64:
+      return run_analysis<double, double>(tb, batch, static_cast<const double *>(map), static_cast<double2 *>(alm),
+                                          tb.rp_w, 1.0, 1.0, 1.0, work, st);
+    case SHTX_F32:
+      return run_analysis<float, float>(tb, batch, static_cast<const float *>(map), static_cast<float2 *>(alm),
+                                        tb.rp_w, 1.0, 1.0, 1.0, work, st);
+    default:
+      return run_analysis<bf16_t, float>(tb, batch, static_cast<const bf16_t *>(map), static_cast<float2 *>(alm),
+                                         tb.rp_w, 1.0, 1.0, 1.0, work, st);
+  }
+}
+
+size_t shtx_noalloc_scratch_bytes(void) { return kScratchBytes; }
+
+int shtx_map2alm_noalloc(int nside, int lmax, int batch, int dtype, const void *map, void *alm, const void *tables,
+                         void *stream) {
+  if (!valid_geom(nside, lmax) || batch < 1) return SHTX_ERR_ARG;
+  if (dtype != SHTX_F64 && dtype != SHTX_F32 && dtype != SHTX_BF16) return SHTX_ERR_ARG;
+  if (nside > kMaxNside) return SHTX_ERR_UNSUPPORTED;
+  // the analysis uses the two spectrum buffers of the workspace layout (the
+  // coefficient buffer after them serves only the synthesis)
+  const size_t cs = dtype == SHTX_F64 ? 16 : 8;
+  size_t nbhat;
+  int mmax_bs;
+  bluestein_sizes(nside, &nbhat, &mmax_bs);
+  const size_t need = 2 * align_up(spec_bytes(nside, lmax, mmax_bs, batch, cs), 256);
+  if (need > kScratchBytes) return SHTX_ERR_SCRATCH;
+  int s = SHTX_OK;
+  void *work = scratch_ptr(&s);
+  if (!work) return s;
+  Tables tb;
+  // the scratch stands in for a workspace (check_common's size test is met by
+  // construction: only the spectrum buffers are touched)
+  s = check_common(nside, lmax, batch, dtype, map, alm, tables, work, shtx_workspace_bytes(nside, lmax, batch, dtype),
+                   &tb, true);
   if (s != SHTX_OK) return s;
   hipStream_t st = static_cast<hipStream_t>(stream);
   switch (dtype) {

@@ -27,7 +27,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_status_strings():
     L = _lib.lib()
-    for s in range(6):
+    for s in range(7):
         assert L.shtx_status_string(s)
     assert L.shtx_version() >= 100
 
@@ -148,3 +148,14 @@ def test_weighted_analysis_validation_before_launch():
     assert f(6, 15, 2, 1, FAKE, FAKE, FAKE, FAKE, FAKE, wb, None) == _lib.ERR_ARG
     assert f(8, 15, 2, 1, FAKE, FAKE, FAKE, FAKE, FAKE, wb, None) == _lib.ERR_TABLES   # tables never built
 
+
+def test_noalloc_limit_checked_before_any_gpu_work():
+    """The allocation-free analysis rejects requests beyond its fixed scratch
+    (SHTX_ERR_SCRATCH) and invalid arguments before touching the device."""
+    L = _lib.lib()
+    cap = L.shtx_noalloc_scratch_bytes()
+    assert cap == 64 << 20
+    assert L.shtx_map2alm_noalloc(1024, 2047, 16, 1, FAKE, FAKE, FAKE, None) == _lib.ERR_SCRATCH
+    assert L.shtx_map2alm_noalloc(6, 15, 2, 1, FAKE, FAKE, FAKE, None) == _lib.ERR_ARG
+    assert L.shtx_map2alm_noalloc(8, 15, 0, 1, FAKE, FAKE, FAKE, None) == _lib.ERR_ARG
+    assert L.shtx_map2alm_noalloc(8, 15, 2, 5, FAKE, FAKE, FAKE, None) == _lib.ERR_ARG
