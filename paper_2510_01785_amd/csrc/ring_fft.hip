@@ -34,6 +34,26 @@ __device__ __forceinline__ int lstride(int s, int pad) { return pad ? s + (s >> 
 inline size_t lds_elems(size_t n) { return n + (n >> 4) + 1; }
 constexpr int kPadMin = 256;  // transform length from which the buffer is padded
 
+// Lanes per fold item of the inverse: on short rings every k collects many
+// aliases m = +-k mod n (about (lmax + 1) / n per direction), so the aliases
+// of one item are dealt to S consecutive lanes of a wave (S a power of two,
+// at most 64 and at most the alias count), as long as the items times S fit
+// in the workgroup; the lanes' partial sums are added by a fixed butterfly of
+// shuffles (deterministic).  Uniform across the workgroup.
+__device__ __forceinline__ int fold_lanes(int items, int n, int M, int NT) {
+  const int aliases = (M + n - 1) / n;
+  int S = 1;
+  while (S < 64 && 2 * S * items <= NT && S < aliases) S <<= 1;
+  return S;
+}
+template <typename C> __device__ __forceinline__ C group_sum(C v, int S) {
+  for (int o = 1; o < S; o <<= 1) {
+    v.x += __shfl_xor(v.x, o);
+    v.y += __shfl_xor(v.y, o);
+  }
+  return v;
+}
+
 // w^e = exp(-2 pi i e / N) for 0 <= e < N from an octant table in LDS,
 // tq[r] = w^r for r = 0..N/8 (N = 4 << lq): with e = q N/4 + r,
 // w^e = (-i)^q w^r, and for r > N/8, w^r = (sin phi, -cos phi) where
@@ -379,8 +399,11 @@ __device__ __forceinline__ void stage_mix_p2(cplx<T> *buf, int n, int G, int p, 
   __syncthreads();
 }
 
-// Stage of odd radix R (span p): thread per output,
+// Stage of odd radix R (span p, R <= kMaxDirectPrime): thread per output,
 //   y[g pR + q p + k] = sum_r x[g p + k + r n/R] w^{r (n/(pR)) (k + q p)}.
+// The root-table loads of an output are issued four at a time (indices by
+// integer adds), so an output waits for ceil((R - 1) / 4) load latencies
+// rather than for R - 1 in a row.
 template <typename T, int NT>
 __device__ __forceinline__ void stage_odd(cplx<T> *buf, int n, int G, int p, int R, int pad,
                                           const cplx<T> *__restrict__ roots) {
@@ -406,10 +429,18 @@ __device__ __forceinline__ void stage_odd(cplx<T> *buf, int n, int G, int p, int
       const int be = step * (k + q * p);
       C acc = buf[lidx(xb, pad)];
       int e = be;
-      for (int r = 1; r < R; ++r) {
-        acc = cadd(acc, cmul(buf[lidx(xb + r * Tn, pad)], roots[e]));
-        e += be;
-        if (e >= n) e -= n;
+#pragma unroll 1
+      for (int r0 = 1; r0 < R; r0 += 4) {
+        C wr[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          if (r0 + u < R) wr[u] = roots[e];
+          e += be;
+          if (e >= n) e -= n;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (r0 + u < R) acc = cadd(acc, cmul(buf[lidx(xb + (r0 + u) * Tn, pad)], wr[u]));
       }
       out[s] = acc;
     }
@@ -507,7 +538,7 @@ template <int NT> struct BsSlots {  // values of s < i per thread (i < kMaxNside
 // octant table of M.
 template <typename T, int NT, typename In>
 __device__ __forceinline__ void ring_dft_bs4(const Tables &tb, int p, int M, int nb, int gc, cplx<T> *buf,
-                                             cplx<T> *tq, int n, bool tq_ready, In input) {
+                                             cplx<T> *tq, int n, bool tq_ready, In input, int S = 1) {
   using C = cplx<T>;
   constexpr int NS = BsSlots<NT>::value;
   const int i = n >> 2;
@@ -531,9 +562,25 @@ __device__ __forceinline__ void ring_dft_bs4(const Tables &tb, int p, int M, int
   for (int q0 = 0; q0 < 4; q0 += nb) {
     tid = threadIdx.x;
     asm volatile("" : "+v"(tid));
-    for (int e = tid; e < gc * nb * i; e += NT) {
-      const int cc = e / i, j = e - cc * i;  // convolution channel cc = (channel, sub-transform)
-      wb[cc * cs + lidx(j, padM)] = input(cc / nb, 4 * j + q0 + cc % nb);
+    if (S == 1) {
+      for (int e = tid; e < gc * nb * i; e += NT) {
+        const int cc = e / i, j = e - cc * i;  // convolution channel cc = (channel, sub-transform)
+        wb[cc * cs + lidx(j, padM)] = input(cc / nb, 4 * j + q0 + cc % nb, 0, 1);
+      }
+    } else {
+      // S lanes per sample, each returning its share (a wave-uniform loop:
+      // every lane of a wave takes part in the shuffles)
+      const int ls = __builtin_ctz(S), tot = (gc * nb * i) << ls;
+      for (int e0 = tid & ~63; e0 < tot; e0 += NT) {
+        const int e = e0 + (tid & 63);
+        const bool ok = e < tot;
+        const int it = e >> ls, r = e & (S - 1);
+        const int cc = it / i, j = it - cc * i;
+        C v = cmk<C>(0, 0);
+        if (ok) v = input(cc / nb, 4 * j + q0 + cc % nb, r, S);
+        v = group_sum(v, S);
+        if (ok && r == 0) wb[cc * cs + lidx(j, padM)] = v;
+      }
     }
     __syncthreads();
 #pragma unroll 1
@@ -790,7 +837,7 @@ __global__ void __launch_bounds__(NT, sizeof(T) == 4 ? 4 : 1)
     const int gc = min(Gp, bg1 - b0);
     if (Mbs) {
       // Bluestein ring: samples read per sub-transform, packed on the fly
-      auto input = [&](int c, int k) {
+      auto input = [&](int c, int k, int, int) {
         const TIn *row = map + (size_t)(b0 + c) * npix;
         const int kN = NEST ? (int)tb.r2n[sN + k] : sN + k;
         const int kS = NEST ? (int)tb.r2n[sS + k] : sS + k;
@@ -880,6 +927,7 @@ __global__ void __launch_bounds__(NT, sizeof(T) == 4 ? 4 : 1)
 
 constexpr int kFoldUnroll = 2;  // (k, channel) items per thread with loads in flight
 
+
 template <typename TOut, typename T, int NT>
 __global__ void __launch_bounds__(NT, sizeof(T) == 4 ? 4 : 1)
     k_ring_fft_inv(Tables tb, int B, int G, int tq_off, int bs_nb, const cplx<T> *__restrict__ GN,
@@ -961,6 +1009,61 @@ __global__ void __launch_bounds__(NT, sizeof(T) == 4 ? 4 : 1)
     fold_sums(gn, gs, k, c, pn, ps, qn, qs, cn, cs);
     return cmk<C>(cn.x - cs.y, -(cn.y + cs.x));
   };
+  // The share of lane r of S (0 <= r < S) in C_N, C_S at k: lane 0 takes the
+  // base terms m1 = k and m2 = n - k (as fold_sums), lane r the aliases
+  // m1 + t n and m2 + t n with t >= 1, t = r mod S.  With S even the aliases
+  // of one lane share m mod 2n, so their phase is applied once to their sum.
+  auto fold_part = [&](const C *gn, const C *gs, int k, int c, int r, int S, C &cn, C &cs) {
+    cn = cmk<C>(0, 0);
+    cs = cmk<C>(0, 0);
+    const int m1 = k, m2 = (k == 0) ? n : n - k;
+    if (r == 0) {
+      C pn, ps, qn, qs;
+      fold_load(gn, gs, k, c, pn, ps, qn, qs);
+      if (m1 < M) {
+        const C ph = rph.plus(m1);
+        cn = cmul(pn, ph);
+        cs = cmul(ps, ph);
+        if (m1 == 0) {
+          cn.y = 0;
+          cs.y = 0;
+        }
+      }
+      if (m2 < M) {
+        const C ph = rph.plus(m2);
+        cn = cadd(cn, cconj(cmul(qn, ph)));
+        cs = cadd(cs, cconj(cmul(qs, ph)));
+      }
+    }
+    const int t0 = r == 0 ? S : r;
+    // positive frequencies: m = m1 + t n
+    {
+      C an = cmk<C>(0, 0), as = cmk<C>(0, 0);
+      const int mm = m1 + (t0 & 1) * n;  // m mod 2n (the same for every t of this lane)
+#pragma unroll 4
+      for (int m = m1 + t0 * n; m < M; m += S * n) {
+        an = cadd(an, gn[(size_t)m * B + c]);
+        if (!equator) as = cadd(as, gs[(size_t)m * B + c]);
+      }
+      const C ph = rph.plus(mm);
+      cn = cadd(cn, cmul(an, ph));
+      cs = cadd(cs, cmul(as, ph));
+    }
+    // negative frequencies: m = m2 + t n, conjugated
+    {
+      C an = cmk<C>(0, 0), as = cmk<C>(0, 0);
+      int mm = m2 + (t0 & 1) * n;
+      if (mm >= 2 * n) mm -= 2 * n;
+#pragma unroll 4
+      for (int m = m2 + t0 * n; m < M; m += S * n) {
+        an = cadd(an, gn[(size_t)m * B + c]);
+        if (!equator) as = cadd(as, gs[(size_t)m * B + c]);
+      }
+      const C ph = rph.plus(mm);
+      cn = cadd(cn, cconj(cmul(an, ph)));
+      cs = cadd(cs, cconj(cmul(as, ph)));
+    }
+  };
 #pragma unroll 1
   for (int b0 = bg0; b0 < bg1; b0 += Gp) {
     // opaque thread index per channel pass: keeps the pass's index and
@@ -972,17 +1075,44 @@ __global__ void __launch_bounds__(NT, sizeof(T) == 4 ? 4 : 1)
     const C *gs = GS + sbase + (b0 - bg0);
     if (Mbs) {
       // Bluestein ring: folded values computed per sub-transform sample
-      auto input = [&](int c, int k) {
-        C pn, ps, qn, qs;
-        fold_load(gn, gs, k, c, pn, ps, qn, qs);
-        return fold_value(gn, gs, k, c, pn, ps, qn, qs);
+      auto input = [&](int c, int k, int r, int S) {
+        if (S == 1) {
+          C pn, ps, qn, qs;
+          fold_load(gn, gs, k, c, pn, ps, qn, qs);
+          return fold_value(gn, gs, k, c, pn, ps, qn, qs);
+        }
+        C cn, cs;
+        fold_part(gn, gs, k, c, r, S, cn, cs);
+        return cmk<C>(cn.x - cs.y, -(cn.y + cs.x));
       };
-      ring_dft_bs4<T, NT>(tb, p, Mbs, bs_nb, gc, buf, tq, n, b0 != bg0, input);
+      ring_dft_bs4<T, NT>(tb, p, Mbs, bs_nb, gc, buf, tq, n, b0 != bg0, input,
+                          fold_lanes(gc * min(bs_nb, 4) * (n >> 2), n, M, NT));
     } else {
       // k = 0..n/2; each item also writes k' = n - k (conjugate sums)
       const int nk = gc * ((n >> 1) + 1);
+      const int S = fold_lanes(nk, n, M, NT);
+      if (S > 1) {
+        // short ring: S lanes per item (a wave-uniform loop: every lane of a
+        // wave takes part in the shuffles)
+        const int ls = __builtin_ctz(S), tot = nk << ls;
 #pragma unroll 1
-      for (int j0 = tid; j0 < nk; j0 += kFoldUnroll * NT) {
+        for (int e0 = tid & ~63; e0 < tot; e0 += NT) {
+          const int e = e0 + (tid & 63);
+          const bool ok = e < tot;
+          const int j = e >> ls, r = e & (S - 1);
+          const int k = j / gc, c = j - k * gc;
+          C cn = cmk<C>(0, 0), cs = cmk<C>(0, 0);
+          if (ok) fold_part(gn, gs, k, c, r, S, cn, cs);
+          cn = group_sum(cn, S);
+          cs = group_sum(cs, S);
+          if (ok && r == 0) {
+            buf[lidx(c * n + k, pad)] = cmk<C>(cn.x - cs.y, -(cn.y + cs.x));
+            if (k != 0 && 2 * k != n) buf[lidx(c * n + n - k, pad)] = cmk<C>(cn.x + cs.y, cn.y - cs.x);
+          }
+        }
+      }
+#pragma unroll 1
+      for (int j0 = tid; S == 1 && j0 < nk; j0 += kFoldUnroll * NT) {
         C pn[kFoldUnroll], ps[kFoldUnroll], qn[kFoldUnroll], qs[kFoldUnroll];
 #pragma unroll
         for (int u = 0; u < kFoldUnroll; ++u) {
