@@ -55,6 +55,9 @@ def parse():
     ap.add_argument("--rate", type=float, default=200.0)
     ap.add_argument("--budget-gib", type=float, default=48.0)
     ap.add_argument("--slots", type=int, default=8)
+    ap.add_argument("--merge-channels", type=int, default=64,
+                    help="serving: merge queued requests of one geometry into calls of up to this many "
+                         "channels (0: every request its own call)")
     ap.add_argument("--peaks", action="store_true",
                     help="only measure the device's HBM copy bandwidth and GEMM (matrix-core) rates "
                          "with torch library calls, print one JSON line and exit")
@@ -224,7 +227,7 @@ def run_serving(args):
         shtx.map2alm_raw(x, lmax) if d == "map2alm" else shtx.alm2map_raw(x, nside, lmax)
     torch.cuda.synchronize()
     budget = int(args.budget_gib * (1 << 30))
-    srv = Server(dev, budget_bytes=budget, slots=args.slots)
+    srv = Server(dev, budget_bytes=budget, slots=args.slots, max_merge_channels=args.merge_channels)
     print("[bench] serving loop run", flush=True)
     errors = []
 
@@ -271,11 +274,12 @@ def run_serving(args):
         "p99_ms": round(st["p99_ms"], 3),
         "queue_wait_p99_ms": round(st["queue_wait_p99_ms"], 3),
         "peak_in_use_gib": round(st["peak_in_use_bytes"] / (1 << 30), 3),
+        "launches": st["launches"],
         "one_at_a_time": {"maps_per_s": round(maps / wall1, 3), "p50_ms": round(float(np.percentile(lat, 50)), 3),
                           "p99_ms": round(float(np.percentile(lat, 99)), 3)},
         "config": {"workload": "healpix_sht_serving", "requests": n, "rate_per_s": args.rate,
                    "nside": nsides, "lmax": "2N-1 or 3N-1", "channels": "1..32", "direction": "50/50",
-                   "budget_gib": args.budget_gib, "slots": args.slots},
+                   "budget_gib": args.budget_gib, "slots": args.slots, "merge_channels": args.merge_channels},
     }
     print(json.dumps(out), flush=True)
 

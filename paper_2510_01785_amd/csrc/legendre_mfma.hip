@@ -362,28 +362,20 @@ __global__ void __launch_bounds__(64)
 #pragma unroll
     for (int u = 0; u < 8; ++u) an[u] = Ag[la + u];
     float lam[8];
-    if (lq <= wlast) {  // uniform: some ring starts at lq
+    // a ring's state is exactly zero before its seed, so the seed enters as a
+    // 0/1 factor on two fused multiply-adds (no selects, no branch)
+    const double f = (lq == ls) ? 1.0 : 0.0;
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const double nx = fma(ac[u] * z, cur, -prv);
-        if (u == 0) {
-          const bool inj = (lq == ls);
-          prv = inj ? sd.x : cur;
-          cur = inj ? sd.y : nx;
-        } else {
-          prv = cur;
-          cur = nx;
-        }
-        lam[u] = (float)cur;
-      }
-    } else {
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const double nx = fma(ac[u] * z, cur, -prv);
+    for (int u = 0; u < 8; ++u) {
+      const double nx = fma(ac[u] * z, cur, -prv);
+      if (u == 0) {
+        prv = fma(f, sd.x, cur);
+        cur = fma(f, sd.y, nx);
+      } else {
         prv = cur;
         cur = nx;
-        lam[u] = (float)cur;
       }
+      lam[u] = (float)cur;
     }
     float bb[4] = {bc[0], bc[1], bc[2], bc[3]};
     if (lq + 7 > L) {  // last group: l beyond lmax contributes nothing

@@ -9,7 +9,13 @@ of an (nside, lmax) not seen before) fits in what is left of the budget, when
 a stream slot is free: a large request at the head that does not fit yet does
 not hold back smaller ones behind it, but once it has been passed over
 `max_skips` times nothing behind it is admitted until it has started (no
-starvation).  A request runs on its slot's stream and an event marks its end.
+starvation).  Queued requests of the same geometry (direction, nside, lmax, dtype) are
+merged with the admitted one into a single transform call on the
+concatenated channels, up to `max_merge_channels` channels and as far as the
+budget allows: one launch of B channels runs the matrix-core kernels and
+costs much less per map than several small ones, and each request receives
+its own slice of the result.  A request runs on its slot's stream and an
+event marks its end.
 A completion thread resolves the futures in completion order, then returns
 the request's transient memory and its slot, which admits the next requests.
 Tables stay resident once built, so their bytes stay charged to the budget.
@@ -27,7 +33,9 @@ Tables stay resident once built, so their bytes stay charged to the budget.
 The scheduling core (`Scheduler`) is independent of the device: it drives an
 executor with `need(req)` (bytes held while the request runs, or a pair
 (those bytes, bytes that stay resident once it has run)), `launch(req,
-slot)`, `done(handle)` and `finish(handle)`.  `Server` pairs it with the GPU executor built on the C-ABI
+slot)`, `done(handle)` and `finish(handle)`; an executor that also offers
+`group_key(req)`, `need_group(reqs)` and `launch_group(reqs, slot)` (whose
+`finish` returns one result per request) gets merged requests.  `Server` pairs it with the GPU executor built on the C-ABI
 binding (`ops`); tests drive it with a host executor.
 """
 import collections
@@ -84,8 +92,10 @@ class Scheduler:
     requests that fit admitted ahead of a blocked head at most `max_skips`
     times (default: twice the slot count)."""
 
-    def __init__(self, executor, budget_bytes, slots, poll_s=2e-4, max_skips=None):
+    def __init__(self, executor, budget_bytes, slots, poll_s=2e-4, max_skips=None, max_merge_channels=0):
         self.ex = executor
+        # merging needs the executor's group interface
+        self.max_merge = int(max_merge_channels) if hasattr(executor, "launch_group") else 0
         self.budget = int(budget_bytes)
         self.slots = int(slots)
         self.poll_s = poll_s
@@ -98,6 +108,7 @@ class Scheduler:
         self._launching = 0          # admitted, launch in progress
         self.in_use = 0
         self.peak_in_use = 0
+        self.launches = 0            # transform calls (a merged job is one)
         self.finished = []
         self._closed = False
         self._threads = [threading.Thread(target=self._admit_loop, daemon=True),
@@ -141,18 +152,39 @@ class Scheduler:
 
     # ----------------------------------------------------------- threads
     def _pick_locked(self):
-        """Index of the request to admit now and its (transient, resident)
-        bytes, or None: the first queued request that fits, scanning no
-        further than a request that has been passed over max_skips times."""
+        """Queue indices of the job to admit now (the first queued request
+        that fits, scanning no further than a request that has been passed
+        over max_skips times, plus the queued requests merged with it) and
+        its (transient, resident) bytes, or None."""
         if not self._free_slots:
             return None
         for i, r in enumerate(self._queue):
             t, res = _split_need(self.ex.need(r))
             if self.in_use + t + res <= self.budget:
-                return i, t, res
+                return self._merge_locked(i, t, res)
             if r.skipped >= self.max_skips:
                 return None
         return None
+
+    def _merge_locked(self, i, t, res):
+        """Request i and the later queued requests of its group key that fit
+        (channels up to max_merge_channels, bytes within the budget)."""
+        idx = [i]
+        if self.max_merge <= 0:
+            return idx, t, res
+        head = self._queue[i]
+        key = self.ex.group_key(head)
+        chans = head.batch
+        for j in range(i + 1, len(self._queue)):
+            r = self._queue[j]
+            if r.future.cancelled() or self.ex.group_key(r) != key or chans + r.batch > self.max_merge:
+                continue
+            tj, rj = _split_need(self.ex.need_group([self._queue[k] for k in idx] + [r]))
+            if self.in_use + tj + rj <= self.budget:
+                idx.append(j)
+                chans += r.batch
+                t, res = tj, rj
+        return idx, t, res
 
     def _admit_loop(self):
         while True:
@@ -165,35 +197,43 @@ class Scheduler:
                     if pick is not None:
                         break
                     self._cv.wait(0.05)
-                i, t, res = pick
-                req = self._queue[i]
-                del self._queue[i]
-                for j in range(i):
+                idx, t, res = pick
+                job = [self._queue[k] for k in idx]
+                for k in sorted(idx, reverse=True):
+                    del self._queue[k]
+                for j in range(idx[0]):
                     self._queue[j].skipped += 1
-                if not req.future.set_running_or_notify_cancel():
+                job = [r for r in job if r.future.set_running_or_notify_cancel()]
+                if not job:
                     continue
+                if len(job) < len(idx):  # a request was cancelled meanwhile: recount its job
+                    t, res = _split_need(self.ex.need_group(job) if len(job) > 1 else self.ex.need(job[0]))
                 slot = self._free_slots.pop(0)
-                req.need = t
+                job[0].need = t  # the job's transient bytes, returned when it ends
                 self.in_use += t + res
                 self.resident += res
                 self.peak_in_use = max(self.peak_in_use, self.in_use)
-                req.t_admit = time.perf_counter()
+                now = time.perf_counter()
+                for r in job:
+                    r.t_admit = now
                 self._launching += 1
             try:
-                handle = self.ex.launch(req, slot)
+                handle = self.ex.launch_group(job, slot) if len(job) > 1 else self.ex.launch(job[0], slot)
             except Exception as e:  # launch failed: release and report
                 # resident bytes go back too if the tables were not kept
-                lost = res if _split_need(self.ex.need(req))[1] > 0 else 0
+                lost = res if _split_need(self.ex.need(job[0]))[1] > 0 else 0
                 with self._cv:
-                    self.in_use -= req.need + lost
+                    self.in_use -= job[0].need + lost
                     self.resident -= lost
                     self._free_slots.append(slot)
                     self._launching -= 1
                     self._cv.notify_all()
-                req.future.set_exception(e)
+                for r in job:
+                    r.future.set_exception(e)
                 continue
             with self._cv:
-                self._running[slot] = (req, handle)
+                self._running[slot] = (job, handle)
+                self.launches += 1
                 self._launching -= 1
                 self._cv.notify_all()
 
@@ -217,26 +257,31 @@ class Scheduler:
                     return
                 running = list(self._running.items())
             done_any = False
-            for slot, (req, handle) in running:
+            for slot, (job, handle) in running:
                 if not self.ex.done(handle):
                     continue
                 try:
                     result = self.ex.finish(handle)
+                    results = result if len(job) > 1 else [result]
                     err = None
                 except Exception as e:
-                    result, err = None, e
-                req.t_done = time.perf_counter()
+                    results, err = None, e
+                now = time.perf_counter()
                 with self._cv:
                     del self._running[slot]
-                    self.in_use -= req.need
+                    self.in_use -= job[0].need
                     self._free_slots.append(slot)
-                    # timing record only: the result stays with the caller's future
-                    self.finished.append(Done(req.t_arrival, req.t_admit, req.t_done, req.batch, req.need))
+                    # timing records only: the results stay with the callers' futures
+                    for r in job:
+                        r.t_done = now
+                        self.finished.append(Done(r.t_arrival, r.t_admit, r.t_done, r.batch,
+                                                  job[0].need if r is job[0] else 0))
                     self._cv.notify_all()
-                if err is None:
-                    req.future.set_result(result)
-                else:
-                    req.future.set_exception(err)
+                for k, r in enumerate(job):
+                    if err is None:
+                        r.future.set_result(results[k])
+                    else:
+                        r.future.set_exception(err)
                 done_any = True
             if not done_any:
                 time.sleep(self.poll_s)
@@ -256,7 +301,7 @@ class Scheduler:
         t0 = min(r.t_arrival for r in fin) if t0 is None else t0
         t1 = max(r.t_done for r in fin) if t1 is None else t1
         maps = sum(r.batch for r in fin)
-        return dict(requests=len(fin), maps=maps, maps_per_s=maps / max(t1 - t0, 1e-12),
+        return dict(requests=len(fin), launches=self.launches, maps=maps, maps_per_s=maps / max(t1 - t0, 1e-12),
                     p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
                     queue_wait_p50_ms=float(np.percentile(wait, 50)),
                     queue_wait_p99_ms=float(np.percentile(wait, 99)),
@@ -285,24 +330,49 @@ class GpuExecutor:
         esize = 8 if req.data.dtype == self.torch.complex128 else 4
         return B * self.ops.npix(req.nside) * esize
 
-    def need(self, req):
+    def _code(self, req):
         from . import _lib
         if req.direction == "map2alm":
-            code = {self.torch.float64: _lib.F64, self.torch.float32: _lib.F32,
+            return {self.torch.float64: _lib.F64, self.torch.float32: _lib.F32,
                     self.torch.bfloat16: _lib.BF16}[req.data.dtype]
-        elif req.direction == "alm2map":
-            code = {self.torch.complex128: _lib.F64, self.torch.complex64: _lib.F32}[req.data.dtype]
-        else:
-            raise ValueError("unknown direction %r" % req.direction)
+        if req.direction == "alm2map":
+            return {self.torch.complex128: _lib.F64, self.torch.complex64: _lib.F32}[req.data.dtype]
+        raise ValueError("unknown direction %r" % req.direction)
+
+    def need(self, req):
+        return self.need_group([req])
+
+    def group_key(self, req):
+        """Requests with equal keys can run as one transform call (batched
+        2-D inputs; a 1-D single map stays on its own)."""
+        if req.data.dim() != 2:
+            return ("alone", id(req))
+        return (req.direction, req.nside, req.lmax, req.data.dtype)
+
+    def need_group(self, reqs):
+        """(transient, resident) bytes of one call on the requests' channels:
+        outputs, workspace, the concatenated input when there are several,
+        and the tables of an (nside, lmax) not yet resident."""
+        from . import _lib
+        r0 = reqs[0]
+        code = self._code(r0)
         L = _lib.lib()
-        ws = L.shtx_workspace_bytes(req.nside, req.lmax, req.batch, code)
+        B = sum(r.batch for r in reqs)
+        ws = L.shtx_workspace_bytes(r0.nside, r0.lmax, B, code)
+        cat = sum(r.data.numel() * r.data.element_size() for r in reqs) if len(reqs) > 1 else 0
         with self._tables_lock:
-            known = (req.nside, req.lmax) in self._tables
-        tab = 0 if known else L.shtx_tables_bytes(req.nside, req.lmax)
-        return self._out_bytes(req) + ws, tab
+            known = (r0.nside, r0.lmax) in self._tables
+        tab = 0 if known else L.shtx_tables_bytes(r0.nside, r0.lmax)
+        return sum(self._out_bytes(r) for r in reqs) + ws + cat, tab
 
     def launch(self, req, slot):
+        return self.launch_group([req], slot)
+
+    def launch_group(self, reqs, slot):
+        """One transform call on the channels of `reqs` (same group key),
+        each request's result a slice of the output."""
         torch, ops = self.torch, self.ops
+        req = reqs[0]
         key = (req.nside, req.lmax)
         with self._tables_lock:
             ev_tab = self._tables.get(key)
@@ -318,28 +388,39 @@ class GpuExecutor:
         st.wait_event(ev_tab)
         st.wait_stream(torch.cuda.current_stream(self.device))  # inputs written before submit
         with torch.cuda.stream(st):
+            x = req.data if len(reqs) == 1 else torch.cat([r.data for r in reqs], dim=0)
             if req.direction == "map2alm":
-                out = ops.map2alm_raw(req.data, req.lmax)
+                out = ops.map2alm_raw(x, req.lmax)
             else:
-                out = ops.alm2map_raw(req.data, req.nside, req.lmax)
+                out = ops.alm2map_raw(x, req.nside, req.lmax)
             ev = torch.cuda.Event()
             ev.record(st)
-        return (ev, out)
+        if len(reqs) == 1:
+            return (ev, out, None)
+        bounds = []
+        b = 0
+        for r in reqs:
+            bounds.append((b, b + r.batch))
+            b += r.batch
+        return (ev, out, bounds)
 
     def done(self, handle):
         return handle[0].query()
 
     def finish(self, handle):
         handle[0].synchronize()
-        return handle[1]
+        ev, out, bounds = handle
+        if bounds is None:
+            return out
+        return [out[a:b] for a, b in bounds]
 
 
 class Server:
     """GPU serving loop: `submit(Request) -> Future` of the output tensor."""
 
-    def __init__(self, device="cuda:0", budget_bytes=48 << 30, slots=8):
+    def __init__(self, device="cuda:0", budget_bytes=48 << 30, slots=8, max_merge_channels=64):
         self.executor = GpuExecutor(device, slots)
-        self.scheduler = Scheduler(self.executor, budget_bytes, slots)
+        self.scheduler = Scheduler(self.executor, budget_bytes, slots, max_merge_channels=max_merge_channels)
 
     def submit(self, req):
         return self.scheduler.submit(req)

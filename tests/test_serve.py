@@ -120,6 +120,74 @@ def test_resident_tables_stay_charged():
     s2.close()
 
 
+class GroupExecutor(HostExecutor):
+    """Supports merged jobs: requests with the same lmax tag share a key;
+    need = sum of the members' nside (bytes) plus 1 per merged member."""
+
+    def __init__(self, dur=0.02):
+        super().__init__(dur)
+        self.jobs = []
+
+    def group_key(self, req):
+        return req.lmax
+
+    def need_group(self, reqs):
+        return sum(r.nside for r in reqs) + (len(reqs) - 1)
+
+    def launch_group(self, reqs, slot):
+        with self.lock:
+            self.live += 1
+            self.max_live = max(self.max_live, self.live)
+            self.jobs.append([r.lmax for r in reqs])
+            self.launched.extend((r.lmax, slot) for r in reqs)
+        return [time.perf_counter() + self.dur, reqs]
+
+    def launch(self, req, slot):
+        return self.launch_group([req], slot)
+
+    def finish(self, h):
+        with self.lock:
+            self.live -= 1
+        reqs = h[1]
+        out = [("out", r.lmax, r.batch) for r in reqs]
+        return out if len(reqs) > 1 else out[0]
+
+
+def test_queued_requests_of_one_key_are_merged():
+    """While the only slot is busy, queued requests with the same key are
+    admitted together (channel cap, budget), each future gets its own result."""
+    ex = GroupExecutor(0.03)
+    s = Scheduler(ex, budget_bytes=100, slots=1, max_merge_channels=10)
+    first = s.submit(make(10, "a", batch=2))
+    time.sleep(0.005)
+    later = [s.submit(make(10, k, batch=3)) for k in ("a", "b", "a", "a", "b", "a")]
+    res = [f.result(timeout=10) for f in [first] + later]
+    s.close()
+    assert res[0] == ("out", "a", 2)
+    assert [r[1] for r in res[1:]] == ["a", "b", "a", "a", "b", "a"] and all(r[2] == 3 for r in res[1:])
+    assert ex.jobs[0] == ["a"]
+    # the next job is the queued head "a" with the later "a"s that fit in
+    # 10 channels (3 + 3 + 3), then the "b"s together, then the last "a"
+    assert ex.jobs[1] == ["a", "a", "a"] and ex.jobs[2] == ["b", "b"] and ex.jobs[3] == ["a"]
+    assert s.peak_in_use <= 100 and s.in_use == 0
+    st = s.stats()
+    assert st["requests"] == 7 and st["maps"] == 2 + 6 * 3
+
+
+def test_merge_respects_the_budget():
+    ex = GroupExecutor(0.03)
+    s = Scheduler(ex, budget_bytes=45, slots=1, max_merge_channels=64)
+    first = s.submit(make(20, "x"))
+    time.sleep(0.005)
+    later = [s.submit(make(20, "x")) for _ in range(3)]
+    for f in [first] + later:
+        f.result(timeout=10)
+    s.close()
+    # two members need 20 + 20 + 1 = 41 <= 45; three would need 62
+    assert ex.jobs == [["x"], ["x", "x"], ["x"]]
+    assert s.peak_in_use <= 45
+
+
 def test_over_budget_rejected_without_launch():
     ex = HostExecutor()
     s = Scheduler(ex, budget_bytes=100, slots=2)
@@ -170,7 +238,8 @@ def test_stats_well_formed():
 @pytest.mark.gpu
 def test_gpu_mix_equals_alone():
     """Each request's output is bit-identical alone and in a concurrent mix of
-    several (nside, lmax), directions and batch sizes."""
+    several (nside, lmax), directions and batch sizes; with queued requests
+    of one geometry merged into one call, equal within the FP32 tolerance."""
     import torch
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
@@ -194,7 +263,8 @@ def test_gpu_mix_equals_alone():
     for d, nside, lmax, x in reqs:
         alone.append(shtx.map2alm_raw(x, lmax) if d == "map2alm" else shtx.alm2map_raw(x, nside, lmax))
     torch.cuda.synchronize()
-    srv = Server(dev, budget_bytes=2 << 30, slots=4)
+    # without merging: every request is its own call, bit-identical to alone
+    srv = Server(dev, budget_bytes=2 << 30, slots=4, max_merge_channels=0)
     futs = [srv.submit(Request(d, nside, lmax, x)) for d, nside, lmax, x in reqs]
     outs = [f.result(timeout=60) for f in futs]
     st = srv.stats()
@@ -203,6 +273,18 @@ def test_gpu_mix_equals_alone():
     for a, o in zip(alone, outs):
         assert torch.equal(a, o)
     assert st["requests"] == 12 and st["peak_in_use_bytes"] <= 2 << 30
+    # with merging (one slot, so that queued requests of one geometry merge):
+    # a merged call may take the matrix-core kernels where the request alone
+    # took the vector ones, so the results agree to the FP32 tolerance
+    srv = Server(dev, budget_bytes=2 << 30, slots=1, max_merge_channels=64)
+    futs = [srv.submit(Request(d, nside, lmax, x)) for d, nside, lmax, x in reqs]
+    merged = [f.result(timeout=60) for f in futs]
+    srv.close()
+    torch.cuda.synchronize()
+    for a, o in zip(alone, merged):
+        assert o.shape == a.shape
+        err = float(torch.linalg.vector_norm((o - a).flatten()) / torch.linalg.vector_norm(a.flatten()))
+        assert err <= 1e-5, err
     # and each served result is the transform: FP32 parity with the FP64 oracle
     from oracle import sht
     for (d, nside, lmax, x), o in zip(reqs, outs):
