@@ -54,7 +54,7 @@ def parse():
     ap.add_argument("--requests", type=int, default=2000)
     ap.add_argument("--rate", type=float, default=200.0)
     ap.add_argument("--budget-gib", type=float, default=48.0)
-    ap.add_argument("--slots", type=int, default=8)
+    ap.add_argument("--slots", type=int, default=4)
     ap.add_argument("--merge-channels", type=int, default=64,
                     help="serving: merge queued requests of one geometry into calls of up to this many "
                          "channels (0: every request its own call)")

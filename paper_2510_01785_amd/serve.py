@@ -418,7 +418,7 @@ class GpuExecutor:
 class Server:
     """GPU serving loop: `submit(Request) -> Future` of the output tensor."""
 
-    def __init__(self, device="cuda:0", budget_bytes=48 << 30, slots=8, max_merge_channels=64):
+    def __init__(self, device="cuda:0", budget_bytes=48 << 30, slots=4, max_merge_channels=64):
         self.executor = GpuExecutor(device, slots)
         self.scheduler = Scheduler(self.executor, budget_bytes, slots, max_merge_channels=max_merge_channels)
 
