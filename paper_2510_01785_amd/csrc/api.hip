@@ -17,8 +17,9 @@ hipError_t launch_tables_build(int nside, int lmax, void *base, hipStream_t st);
 template <typename TIn, typename T, typename TS>
 hipError_t launch_ring_fft_fwd(Tables, int, const TIn *, const double *, double, const double *, TS *, TS *,
                                hipStream_t, bool);
-hipError_t launch_legendre_fwd_bf16(const Tables &, int, const uint32_t *, const uint32_t *, float2 *, double, double,
-                                    int, hipStream_t, const uint32_t *);
+hipError_t launch_legendre_fwd_bf16(const Tables &, int, const uint32_t *, const uint32_t *, void *, float2 *, double,
+                                    double, int, hipStream_t, const uint32_t *);
+size_t bf16_packed_spectra_bytes(int lmax, int npairs, int B);
 size_t lam_header_words(int nside, int nitems);
 std::vector<uint32_t> lam_tile_offsets(int nside, int lmax, int nitems, const uint8_t *ck_t, const int2 *items,
                                        size_t *ntiles);
@@ -274,7 +275,9 @@ int run_analysis(const Tables &tb, int B, const TIn *map, cplx<T> *alm, const do
       }
       if (e != hipSuccess) return SHTX_ERR_HIP;
       StageTimer t(kStLegFwd, st);
-      return status_of(launch_legendre_fwd_bf16(tb, B, sa, sb, alm, f0, fm, accumulate, st, lam));
+      // the spectra in operand order go where the synthesis keeps its
+      // coefficients (unused by the analysis)
+      return status_of(launch_legendre_fwd_bf16(tb, B, sa, sb, w.almt, alm, f0, fm, accumulate, st, lam));
     }
   }
   {
@@ -415,7 +418,10 @@ size_t shtx_workspace_bytes(int nside, int lmax, int batch, int dtype) {
   const size_t spec = spec_bytes(nside, lmax, mmax_bs, batch, cs);
   // coefficients [idx][batch] plus kCoefPad rows read (and masked) past lmax
   const size_t almt = (nalm_of(lmax) + kCoefPad) * (size_t)batch * cs;
-  return 2 * align_up(spec, 256) + align_up(almt, 256);
+  // BF16 maps: the analysis' spectra in matrix-operand order share that room
+  const size_t third =
+      dtype == SHTX_BF16 ? std::max(almt, bf16_packed_spectra_bytes(lmax, 2 * nside, batch)) : almt;
+  return 2 * align_up(spec, 256) + align_up(third, 256);
 }
 
 int shtx_map2alm(int nside, int lmax, int batch, int dtype, const void *map, void *alm, const void *tables,
@@ -444,20 +450,22 @@ int shtx_map2alm_noalloc(int nside, int lmax, int batch, int dtype, const void *
   if (!valid_geom(nside, lmax) || batch < 1) return SHTX_ERR_ARG;
   if (dtype != SHTX_F64 && dtype != SHTX_F32 && dtype != SHTX_BF16) return SHTX_ERR_ARG;
   if (nside > kMaxNside) return SHTX_ERR_UNSUPPORTED;
-  // the analysis uses the two spectrum buffers of the workspace layout (the
-  // coefficient buffer after them serves only the synthesis)
+  // the analysis uses the two spectrum buffers of the workspace layout and,
+  // for BF16 maps, the operand-order spectra after them (the coefficient
+  // buffer serves only the synthesis)
   const size_t cs = dtype == SHTX_F64 ? 16 : 8;
   size_t nbhat;
   int mmax_bs;
   bluestein_sizes(nside, &nbhat, &mmax_bs);
-  const size_t need = 2 * align_up(spec_bytes(nside, lmax, mmax_bs, batch, cs), 256);
+  size_t need = 2 * align_up(spec_bytes(nside, lmax, mmax_bs, batch, cs), 256);
+  if (dtype == SHTX_BF16) need += align_up(bf16_packed_spectra_bytes(lmax, 2 * nside, batch), 256);
   if (need > kScratchBytes) return SHTX_ERR_SCRATCH;
   int s = SHTX_OK;
   void *work = scratch_ptr(&s);
   if (!work) return s;
   Tables tb;
   // the scratch stands in for a workspace (check_common's size test is met by
-  // construction: only the spectrum buffers are touched)
+  // construction: only the buffers counted in `need` are touched)
   s = check_common(nside, lmax, batch, dtype, map, alm, tables, work, shtx_workspace_bytes(nside, lmax, batch, dtype),
                    &tb, true);
   if (s != SHTX_OK) return s;

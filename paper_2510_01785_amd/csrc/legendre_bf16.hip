@@ -74,8 +74,8 @@ constexpr int kLamTileBytes = kLamTileW * 4;
 
 template <int MODE>
 __global__ void __launch_bounds__(256)
-    k_legendre_fwd_bf16(Tables tb, int B, const double *__restrict__ coefA, const uint32_t *__restrict__ XE,
-                        const uint32_t *__restrict__ XO, float2 *__restrict__ alm, float f0, float fm, int accum,
+    k_legendre_fwd_bf16(Tables tb, int B, const double *__restrict__ coefA, const u32x4_t *__restrict__ XT,
+                        size_t xt_par, float2 *__restrict__ alm, float f0, float fm, int accum,
                         const uint32_t *__restrict__ lam_off, uint32_t *__restrict__ lam_tiles) {
   const int b0 = 16 * blockIdx.y;  // channel group of this row of the grid
   __shared__ __attribute__((aligned(16))) uint32_t tile[kBfWaves * kBfTileW + 512];
@@ -96,7 +96,10 @@ __global__ void __launch_bounds__(256)
   }
   __syncthreads();
   uint32_t *tw = tile + w * kBfTileW;
-  const bool fast_x = (B & 3) == 0;  // 16-byte spectrum pieces are aligned
+  const int nrb = (Rp + 7) / 8;
+  // B operands of this lane in the packed spectra: (parity, m) rows of the
+  // channel group, 16 bytes per (ring block, column)
+  const u32x4_t *xt = MODE == kLamBuild ? nullptr : XT + ((size_t)blockIdx.y * M + m) * nrb * 32 + col;
 
   f32x16_t acc[4];
 #pragma unroll
@@ -145,61 +148,19 @@ __global__ void __launch_bounds__(256)
       toff = __builtin_amdgcn_readfirstlane(lam_off[(size_t)item * nslices + q0 / kBfSlice]);
     }
 
-    // spectra of the slice -> B operands: staging [col][ring pair] words
-    // (row stride kBfRS), each word the two rings of one pair; a lane loads
-    // 16-byte pieces (4 channels) of rings 2q and 2q + 1, q = lane % 32 +
-    // 32 t, piece lane / 32 + 2 u
+    // B operands of the slice: K step k of lane half h is ring block
+    // q0 / 8 + 2 k + h (clamped: blocks past the last ring pair meet zero
+    // lambdas); issued here, first needed after the recurrence of the first
+    // half block
     u32x4_t xop[2][8];
+    if constexpr (MODE != kLamBuild) {
 #pragma unroll
-    for (int par = 0; par < 2; ++par) {
-      if constexpr (MODE == kLamBuild) break;  // the table build needs no spectra
-      const uint32_t *X = par ? XO : XE;
-      uint32_t pa[2][2][4], pb[2][2][4];
+      for (int par = 0; par < 2; ++par)
 #pragma unroll
-      for (int t = 0; t < 2; ++t)
-#pragma unroll
-        for (int u = 0; u < 2; ++u) {
-          const int q = (j & 31) + 32 * t, c4 = (j >> 5) + 2 * u;
-          const int ra_ = min(q0 + 2 * q, Rp - 1), rb_ = min(q0 + 2 * q + 1, Rp - 1);
-          const size_t oa = ((size_t)ra_ * M + m) * B, ob = ((size_t)rb_ * M + m) * B;
-          const int cb = b0 + 4 * c4;
-          if (fast_x && cb + 3 < B) {
-            const uint4 va = *reinterpret_cast<const uint4 *>(X + oa + cb);
-            const uint4 vb = *reinterpret_cast<const uint4 *>(X + ob + cb);
-            pa[t][u][0] = va.x; pa[t][u][1] = va.y; pa[t][u][2] = va.z; pa[t][u][3] = va.w;
-            pb[t][u][0] = vb.x; pb[t][u][1] = vb.y; pb[t][u][2] = vb.z; pb[t][u][3] = vb.w;
-          } else {
-            // channels beyond the batch read channel B-1 (finite data; those
-            // columns are never stored)
-#pragma unroll
-            for (int d = 0; d < 4; ++d) {
-              const int c = min(cb + d, B - 1);
-              pa[t][u][d] = X[oa + c];
-              pb[t][u][d] = X[ob + c];
-            }
-          }
+        for (int k = 0; k < 8; ++k) {
+          const int rb = min((q0 >> 3) + 2 * k + h, nrb - 1);
+          xop[par][k] = xt[par * xt_par + (size_t)rb * 32];
         }
-#pragma unroll
-      for (int t = 0; t < 2; ++t)
-#pragma unroll
-        for (int u = 0; u < 2; ++u) {
-          const int q = (j & 31) + 32 * t, c4 = (j >> 5) + 2 * u;
-#pragma unroll
-          for (int d = 0; d < 4; ++d) {
-            const uint32_t a = pa[t][u][d], b = pb[t][u][d];
-            const int n = 8 * c4 + 2 * d;  // column of the real part
-            tw[n * kBfRS + q] = (a & 0xffffu) | (b << 16);
-            tw[(n + 1) * kBfRS + q] = (a >> 16) | (b & 0xffff0000u);
-          }
-        }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-#pragma unroll
-      for (int k = 0; k < 8; ++k) xop[par][k] = *reinterpret_cast<const u32x4_t *>(tw + col * kBfRS + 8 * k + 4 * h);
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
 
     double pa_ = 0.0, ca = 0.0, pb_ = 0.0, cb = 0.0;  // (mu_{l-1}, mu_l) of the two rings
@@ -333,16 +294,56 @@ static int longest_xcd_items(int L) {
   return longest;
 }
 
-hipError_t launch_legendre_fwd_bf16(const Tables &tb, int B, const uint32_t *XE, const uint32_t *XO, float2 *alm,
-                                    double f0, double fm, int accum, hipStream_t st, const uint32_t *lam) {
+// The BF16 ring spectra X_{E/O}[p][m][b] (one 32-bit word per value, Re in
+// the low half) rewritten in the B-operand order of the contraction:
+// XT[parity][g][m][rb][col] holds, for channel 16 g + col / 2 (Re for even
+// col, Im for odd), the BF16 values of ring pairs 8 rb .. 8 rb + 7 in 16
+// bytes (zero past the last ring pair and the batch).  A wave covers two m
+// rows of 32 columns: 128 contiguous bytes per ring pair read (16 channels),
+// 512 per row written.
+__global__ void __launch_bounds__(256)
+    k_pack_spectra_bf16(const uint32_t *__restrict__ XE, const uint32_t *__restrict__ XO, u32x4_t *__restrict__ XT,
+                        int B, int M, int Rp, int nrb, int ng) {
+  const int col = threadIdx.x & 31;
+  const int m = blockIdx.x * 8 + (threadIdx.x >> 5);
+  const int rb = blockIdx.y, g = blockIdx.z % ng, par = blockIdx.z / ng;
+  if (m >= M) return;
+  const uint32_t *X = par ? XO : XE;
+  const int c = 16 * g + (col >> 1), sh = 16 * (col & 1);
+  uint32_t v[8];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const int p = 8 * rb + e;
+    const uint32_t wd = (p < Rp && c < B) ? X[((size_t)p * M + m) * B + c] : 0u;
+    v[e] = (wd >> sh) & 0xffffu;
+  }
+  u32x4_t o;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) o[i] = v[2 * i] | (v[2 * i + 1] << 16);
+  XT[((((size_t)par * ng + g) * M + m) * nrb + rb) * 32 + col] = o;
+}
+
+size_t bf16_packed_spectra_bytes(int lmax, int npairs, int B) {
+  return 2 * (size_t)((B + 15) / 16) * (size_t)(lmax + 1) * (size_t)((npairs + 7) / 8) * 512;
+}
+
+hipError_t launch_legendre_fwd_bf16(const Tables &tb, int B, const uint32_t *XE, const uint32_t *XO, void *xt,
+                                    float2 *alm, double f0, double fm, int accum, hipStream_t st,
+                                    const uint32_t *lam) {
   if (tb.nitems == 0) return hipErrorInvalidValue;
-  const dim3 grid(8 * longest_xcd_items(tb.lmax), (B + 15) / 16);
+  const int M = tb.lmax + 1, Rp = tb.npairs, nrb = (Rp + 7) / 8, ng = (B + 15) / 16;
+  if (2 * ng > 65535 || nrb > 65535) return hipErrorInvalidValue;
+  u32x4_t *XT = static_cast<u32x4_t *>(xt);
+  hipLaunchKernelGGL(k_pack_spectra_bf16, dim3((M + 7) / 8, nrb, 2 * ng), dim3(256), 0, st, XE, XO, XT, B, M, Rp,
+                     nrb, ng);
+  const size_t xt_par = (size_t)ng * M * nrb * 32;
+  const dim3 grid(8 * longest_xcd_items(tb.lmax), ng);
   if (lam) {
     const uint32_t *tiles = lam + lam_header_words(tb.nside, tb.nitems);
-    hipLaunchKernelGGL(k_legendre_fwd_bf16<kLamStored>, grid, dim3(256), 0, st, tb, B, tb.coefA, XE, XO, alm,
+    hipLaunchKernelGGL(k_legendre_fwd_bf16<kLamStored>, grid, dim3(256), 0, st, tb, B, tb.coefA, XT, xt_par, alm,
                        (float)f0, (float)fm, accum, lam, const_cast<uint32_t *>(tiles));
   } else {
-    hipLaunchKernelGGL(k_legendre_fwd_bf16<kLamCompute>, grid, dim3(256), 0, st, tb, B, tb.coefA, XE, XO, alm,
+    hipLaunchKernelGGL(k_legendre_fwd_bf16<kLamCompute>, grid, dim3(256), 0, st, tb, B, tb.coefA, XT, xt_par, alm,
                        (float)f0, (float)fm, accum, nullptr, nullptr);
   }
   return hipGetLastError();
@@ -380,7 +381,7 @@ std::vector<uint32_t> lam_tile_offsets(int nside, int lmax, int nitems, const ui
 hipError_t launch_lambda_table_build(const Tables &tb, uint32_t *lam, hipStream_t st) {
   if (tb.nitems == 0) return hipErrorInvalidValue;
   const dim3 grid(8 * longest_xcd_items(tb.lmax), 1);
-  hipLaunchKernelGGL(k_legendre_fwd_bf16<kLamBuild>, grid, dim3(256), 0, st, tb, 16, tb.coefA, nullptr, nullptr,
+  hipLaunchKernelGGL(k_legendre_fwd_bf16<kLamBuild>, grid, dim3(256), 0, st, tb, 16, tb.coefA, nullptr, (size_t)0,
                      nullptr, 1.f, 1.f, 0, lam, lam + lam_header_words(tb.nside, tb.nitems));
   return hipGetLastError();
 }

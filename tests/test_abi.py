@@ -44,7 +44,12 @@ def test_workspace_closed_form(nside, lmax, batch, dtype, bspec):
     cs = 16 if dtype == 0 else 8
     up = lambda x: (x + 255) // 256 * 256
     spec = (lmax + 1) * 2 * nside * bspec * cs
-    want = 2 * up(spec) + up((nalm(lmax) + 8) * batch * cs)  # 8 padding rows of coefficients
+    third = (nalm(lmax) + 8) * batch * cs  # coefficients, 8 padding rows
+    if dtype == 2:
+        # BF16 maps: or the analysis' spectra in matrix-operand order (groups
+        # of 16 channels x 2 parities x (lmax+1) x blocks of 8 ring pairs x 512 B)
+        third = max(third, 2 * -(-batch // 16) * (lmax + 1) * -(-2 * nside // 8) * 512)
+    want = 2 * up(spec) + up(third)
     assert _lib.lib().shtx_workspace_bytes(nside, lmax, batch, dtype) == want
 
 
