@@ -11,13 +11,14 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libshtx.so")
-SOURCES = ["api.hip", "tables.hip", "ring_fft.hip", "legendre_valu.hip", "legendre_mfma.hip", "legendre_bf16.hip",
-           "layout.hip", "reorder.hip", "resize.hip"]
+SOURCES = ["api.hip", "tables.hip", "ring_fft.hip", "legendre_valu.hip", "legendre_mfma.hip", "legendre_mfma64.hip",
+           "legendre_bf16.hip", "layout.hip", "reorder.hip", "resize.hip"]
 # Per-source flags.  The matrix-core kernels keep their accumulators in
 # ordinary VGPRs (gfx950's unified register file): with AGPR accumulators the
 # compiler copies them between the two register kinds around every
 # contraction phase of the analysis kernel.
 EXTRA = {"legendre_mfma.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+         "legendre_mfma64.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
          "legendre_bf16.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
 
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")

@@ -37,6 +37,10 @@ bool mfma_fwd_supported(const Tables &tb);
 hipError_t launch_legendre_fwd_mfma(const Tables &, int, const float2 *, const float2 *, float2 *, double, double, int,
                                     hipStream_t);
 hipError_t launch_legendre_inv_mfma(const Tables &, int, const float2 *, SynLayout, float2 *, float2 *, hipStream_t);
+hipError_t launch_legendre_fwd_mfma64(const Tables &, int, const double2 *, const double2 *, double2 *, double, double,
+                                      int, hipStream_t);
+hipError_t launch_legendre_inv_mfma64(const Tables &, int, const double2 *, SynLayout, double2 *, double2 *,
+                                      hipStream_t);
 template <typename T, typename TI>
 hipError_t launch_alm_in(int, int, int, const cplx<TI> *, const double *, cplx<T> *, double, double, double,
                          hipStream_t);
@@ -210,6 +214,15 @@ int mfma_min_batch(bool synthesis) {
   const char *e = getenv("SHTX_MFMA_MIN_BATCH");
   return e ? atoi(e) : synthesis ? 8 : 5;
 }
+// FP64 transforms take the FP64 matrix cores from 3 channels for the
+// analysis and 5 for the synthesis (measured at Nside 1024: analysis 2.42 ms
+// against 3.84 ms on the vector ALUs at 4 channels, 2.40 against 1.94 at 2;
+// synthesis 2.30 against 2.36 at 5, 2.29 against 1.69 at 4; the 16-column
+// tiles hold 8 channels); SHTX_MFMA_MIN_BATCH sets both.
+int mfma64_min_batch(bool synthesis) {
+  const char *e = getenv("SHTX_MFMA_MIN_BATCH");
+  return e ? atoi(e) : synthesis ? 5 : 3;
+}
 bool force_valu() {
   const char *e = getenv("SHTX_FORCE_VALU");
   return e && e[0] == '1';
@@ -221,23 +234,35 @@ template <typename T> hipError_t legendre_fwd(const Tables &tb, int B, const cpl
                                               cplx<T> *alm, double f0, double fm, int accum, hipStream_t st) {
   return launch_legendre_fwd_valu<T>(tb, B, XE, XO, alm, f0, fm, accum, st);
 }
+template <> hipError_t legendre_fwd<double>(const Tables &tb, int B, const double2 *XE, const double2 *XO,
+                                            double2 *alm, double f0, double fm, int accum, hipStream_t st) {
+  if (B >= mfma64_min_batch(false) && mfma_fwd_supported(tb) && !force_valu())
+    return launch_legendre_fwd_mfma64(tb, B, XE, XO, alm, f0, fm, accum, st);
+  return launch_legendre_fwd_valu<double>(tb, B, XE, XO, alm, f0, fm, accum, st);
+}
 template <> hipError_t legendre_fwd<float>(const Tables &tb, int B, const float2 *XE, const float2 *XO, float2 *alm,
                                            double f0, double fm, int accum, hipStream_t st) {
   if (B >= mfma_min_batch(false) && mfma_fwd_supported(tb) && !force_valu())
     return launch_legendre_fwd_mfma(tb, B, XE, XO, alm, f0, fm, accum, st);
   return launch_legendre_fwd_valu<float>(tb, B, XE, XO, alm, f0, fm, accum, st);
 }
-// Synthesis Legendre kernel of a call: matrix cores (FP32, enough channels)
-// or vector ALUs; the choice also fixes the channel groups of the
-// coefficient buffer (chan_group): one group of all channels for the matrix
-// cores, the vector-ALU kernels' groups otherwise.
+// Synthesis Legendre kernel of a call: matrix cores (enough channels) or
+// vector ALUs; the choice also fixes the channel groups of the coefficient
+// buffer (chan_group): one group of all channels for the matrix cores, the
+// vector-ALU kernels' groups otherwise.
 template <typename T> bool inv_on_mfma(int B) {
-  return sizeof(T) == 4 && B >= mfma_min_batch(true) && !force_valu();
+  if (force_valu()) return false;
+  return sizeof(T) == 4 ? B >= mfma_min_batch(true) : B >= mfma64_min_batch(true);
 }
 
 template <typename T> hipError_t legendre_inv(const Tables &tb, int B, const cplx<T> *ALMT, SynLayout lay,
                                               cplx<T> *GN, cplx<T> *GS, bool mfma, hipStream_t st) {
   return launch_legendre_inv_valu<T>(tb, B, ALMT, lay, GN, GS, st);
+}
+template <> hipError_t legendre_inv<double>(const Tables &tb, int B, const double2 *ALMT, SynLayout lay,
+                                            double2 *GN, double2 *GS, bool mfma, hipStream_t st) {
+  if (mfma) return launch_legendre_inv_mfma64(tb, B, ALMT, lay, GN, GS, st);
+  return launch_legendre_inv_valu<double>(tb, B, ALMT, lay, GN, GS, st);
 }
 template <> hipError_t legendre_inv<float>(const Tables &tb, int B, const float2 *ALMT, SynLayout lay, float2 *GN,
                                            float2 *GS, bool mfma, hipStream_t st) {

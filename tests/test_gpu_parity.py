@@ -60,8 +60,10 @@ CASES = [
     # nside 256 FP32, 2 + 1 at nside 512 FP64)
     (256, 300, 11, torch.float32),
     (512, 600, 3, torch.float64),
-    # FP64 with several channel groups of the vector-ALU kernels on the grid's
-    # second dimension (groups of 2: 8 groups, and 2 + 2 + 1)
+    # FP64 on the matrix-core kernels (from 3 channels): two 8-channel groups
+    # of the analysis and one 16-channel group of the synthesis, and a partial
+    # group of 5 (the vector-ALU kernels' channel groups of 2, 2 + 2 + 1, are
+    # covered by test_fp64_legendre_paths)
     (64, 191, 16, torch.float64),
     (32, 95, 5, torch.float64),
     # batched FP32 transforms at nside 256, lmax 767, 64 channels: four
@@ -175,6 +177,32 @@ def test_fp32_legendre_paths(shtx, nside, lmax, batch, path, monkeypatch):
     g = shtx.alm2map(a, nside, lmax).cpu().numpy()
     gref = sht.alm2map(a.cpu().numpy().astype(np.complex128), nside, lmax)
     assert rel_l2(g, gref) <= 1e-5
+
+
+@pytest.mark.parametrize("nside,lmax,batch,path", [(32, 95, 16, "mfma"), (16, 47, 19, "mfma"), (8, 31, 1, "mfma"),
+                                                   (64, 255, 9, "mfma"),
+                                                   (32, 95, 5, "valu"), (64, 191, 16, "valu"),
+                                                   (64, 191, 2, "default"), (64, 191, 3, "default")])
+def test_fp64_legendre_paths(shtx, nside, lmax, batch, path, monkeypatch):
+    """FP64 through the matrix-core Legendre kernels (8-channel analysis
+    groups, 16-channel synthesis groups, partial groups, one channel) and the
+    vector-ALU ones (channel groups of 2 and 1), each against the oracle at
+    the FP64 bar, analysis and synthesis."""
+    force, min_batch = _PATH_ENV[path]
+    monkeypatch.setenv("SHTX_FORCE_VALU", force)
+    if min_batch is None:
+        monkeypatch.delenv("SHTX_MFMA_MIN_BATCH", raising=False)
+    else:
+        monkeypatch.setenv("SHTX_MFMA_MIN_BATCH", min_batch)
+    announce("fp64 legendre path %s nside=%d lmax=%d B=%d" % (path, nside, lmax, batch))
+    f = synth.white_map(77, batch, geometry.npix(nside))
+    x = torch.tensor(f, dtype=torch.float64, device="cuda")
+    ref = sht.map2alm(f, lmax, nside)
+    a = shtx.map2alm(x, lmax)
+    assert rel_l2(a.cpu().numpy(), ref) <= 1e-12
+    g = shtx.alm2map(a, nside, lmax).cpu().numpy()
+    gref = sht.alm2map(a.cpu().numpy(), nside, lmax)
+    assert rel_l2(g, gref) <= 1e-12
 
 
 # BF16 gradient maps are the FP32 result rounded to nearest even: each value
