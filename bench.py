@@ -27,6 +27,7 @@ PEAK = {  # MI355X published peaks
     "fp32_vector_TFs": 157.3,
     "fp64_vector_TFs": 78.6,
     "fp32_mfma_TFs": 157.3,
+    "fp64_mfma_TFs": 78.6,
     "bf16_mfma_TFs": 2500.0,
 }
 
@@ -68,13 +69,16 @@ def parse():
 
 
 # Legendre kernels: the library takes the matrix-core kernels for FP32 /
-# BF16 contraction from this many channels up (its default switch points),
-# the vector-ALU kernels otherwise
+# BF16 contraction and for FP64 from this many channels up (its default
+# switch points), the vector-ALU kernels otherwise
 MFMA_MIN_BATCH = {"fwd": 5, "inv": 8}
+MFMA64_MIN_BATCH = {"fwd": 3, "inv": 5}
 
 
 def on_mfma(stage, dtype, batch):
     d = stage.split("_")[1]
+    if dtype == "f64":
+        return batch >= MFMA64_MIN_BATCH[d]
     return dtype in ("f32", "bf16") and batch >= MFMA_MIN_BATCH[d]
 
 
@@ -87,10 +91,14 @@ def stage_kernel(stage, dtype, batch):
     """(kernel symbol, source file) that runs `stage`."""
     if bf16_mfma(stage, dtype, batch):
         return ("k_legendre_fwd_bf16", "legendre_bf16.hip")
+    if stage == "pack_bf16":
+        return ("k_pack_spectra_bf16", "legendre_bf16.hip")
     if stage.startswith("legendre"):
         d = stage.split("_")[1]
-        return ("k_legendre_%s_mfma" % d, "legendre_mfma.hip") if on_mfma(stage, dtype, batch) else \
-            ("k_legendre_%s_valu" % d, "legendre_valu.hip")
+        if not on_mfma(stage, dtype, batch):
+            return ("k_legendre_%s_valu" % d, "legendre_valu.hip")
+        return ("k_legendre_%s_mfma64" % d, "legendre_mfma64.hip") if dtype == "f64" else \
+            ("k_legendre_%s_mfma" % d, "legendre_mfma.hip")
     return {"ring_fft_fwd": ("k_ring_fft_fwd", "ring_fft.hip"),
             "ring_fft_inv": ("k_ring_fft_inv", "ring_fft.hip"),
             "alm_in": ("k_alm_in", "layout.hip")}[stage]
@@ -164,13 +172,14 @@ def oracle_check(nside, lmax, f0, a0_gpu, g0_gpu):
 
 
 def stage_peak(bound, dtype):
-    """Peak (flop/s or B/s) of a stage's bound: FP32 matrix cores for FP32
-    contraction (BF16 maps on the FP32 contraction too), the vector ALUs of
-    the compute precision otherwise."""
+    """Peak (flop/s or B/s) of a stage's bound: the matrix cores of the
+    contraction's precision (FP32, or FP64 at the FP64 rate; BF16 maps on
+    the FP32 contraction count as FP32), the vector ALUs of the compute
+    precision otherwise."""
     if bound == "hbm":
         return PEAK["hbm_GBs"] * 1e9
     if bound == "mfma":
-        return PEAK["fp32_mfma_TFs"] * 1e12
+        return (PEAK["fp64_mfma_TFs"] if dtype == "f64" else PEAK["fp32_mfma_TFs"]) * 1e12
     return (PEAK["fp64_vector_TFs"] if dtype == "f64" else PEAK["fp32_vector_TFs"]) * 1e12
 
 
@@ -794,6 +803,10 @@ def main():
         "ring_fft_fwd": ("hbm", float(npix * B * esize + spec_fwd), "GB/s", PEAK["hbm_GBs"]),
         "ring_fft_inv": ("hbm", float(npix * B * esize + spec_bytes), "GB/s", PEAK["hbm_GBs"]),
         "alm_in": ("hbm", 2.0 * alm_bytes, "GB/s", PEAK["hbm_GBs"]),
+        # BF16 spectra read, operand-order copy written (groups of 16
+        # channels, blocks of 8 ring pairs, 512 bytes per (group, m, block))
+        "pack_bf16": ("hbm", float(spec_fwd + 2 * ((B + 15) // 16) * (lmax + 1) * ((2 * nside + 7) // 8) * 512),
+                      "GB/s", PEAK["hbm_GBs"]),
     }
     if bf16_mfma("legendre_fwd", args.dtype, B):
         # BF16 matrix-core analysis: the BF16 contraction (4 T_exec B flops)

@@ -19,7 +19,7 @@ EXPORTS = ("shtx_version", "shtx_status_string", "shtx_tables_bytes", "shtx_tabl
            "shtx_noalloc_scratch_bytes", "shtx_map2alm_noalloc")
 LAYOUT_RING, LAYOUT_NESTED, LAYOUT_FLAT = 0, 1, 2
 FLAT_ORIGINS = ("S", "E", "N", "W")
-STAGES = ("ring_fft_fwd", "legendre_fwd", "alm_in", "legendre_inv", "ring_fft_inv")
+STAGES = ("ring_fft_fwd", "legendre_fwd", "alm_in", "legendre_inv", "ring_fft_inv", "pack_bf16")
 
 _lib = None
 

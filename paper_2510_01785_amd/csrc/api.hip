@@ -17,8 +17,9 @@ hipError_t launch_tables_build(int nside, int lmax, void *base, hipStream_t st);
 template <typename TIn, typename T, typename TS>
 hipError_t launch_ring_fft_fwd(Tables, int, const TIn *, const double *, double, const double *, TS *, TS *,
                                hipStream_t, bool);
-hipError_t launch_legendre_fwd_bf16(const Tables &, int, const uint32_t *, const uint32_t *, void *, float2 *, double,
-                                    double, int, hipStream_t, const uint32_t *);
+hipError_t launch_pack_spectra_bf16(const Tables &, int, const uint32_t *, const uint32_t *, void *, hipStream_t);
+hipError_t launch_legendre_fwd_bf16(const Tables &, int, const void *, float2 *, double, double, int, hipStream_t,
+                                    const uint32_t *);
 size_t bf16_packed_spectra_bytes(int lmax, int npairs, int B);
 size_t lam_header_words(int nside, int nitems);
 std::vector<uint32_t> lam_tile_offsets(int nside, int lmax, int nitems, const uint8_t *ck_t, const int2 *items,
@@ -48,9 +49,9 @@ hipError_t launch_alm_in(int, int, int, const cplx<TI> *, const double *, cplx<T
 namespace {
 
 // ------------------------------------------------------------ stage timing
-enum Stage { kStFftFwd = 0, kStLegFwd, kStAlmIn, kStLegInv, kStFftInv, kNumStages };
+enum Stage { kStFftFwd = 0, kStLegFwd, kStAlmIn, kStLegInv, kStFftInv, kStPackBf16, kNumStages };
 const char *kStageNames[kNumStages] = {"ring_fft_fwd", "legendre_fwd", "alm_in", "legendre_inv",
-                                       "ring_fft_inv"};
+                                       "ring_fft_inv", "pack_bf16"};
 
 struct Profiler {
   std::mutex mu;
@@ -299,10 +300,15 @@ int run_analysis(const Tables &tb, int B, const TIn *map, cplx<T> *alm, const do
         e = launch_ring_fft_fwd<TIn, T, uint32_t>(tb, B, map, wtab, wscale, pixw, sa, sb, st, nested);
       }
       if (e != hipSuccess) return SHTX_ERR_HIP;
-      StageTimer t(kStLegFwd, st);
       // the spectra in operand order go where the synthesis keeps its
       // coefficients (unused by the analysis)
-      return status_of(launch_legendre_fwd_bf16(tb, B, sa, sb, w.almt, alm, f0, fm, accumulate, st, lam));
+      {
+        StageTimer t(kStPackBf16, st);
+        e = launch_pack_spectra_bf16(tb, B, sa, sb, w.almt, st);
+      }
+      if (e != hipSuccess) return SHTX_ERR_HIP;
+      StageTimer t(kStLegFwd, st);
+      return status_of(launch_legendre_fwd_bf16(tb, B, w.almt, alm, f0, fm, accumulate, st, lam));
     }
   }
   {

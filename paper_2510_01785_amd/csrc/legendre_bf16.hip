@@ -327,15 +327,22 @@ size_t bf16_packed_spectra_bytes(int lmax, int npairs, int B) {
   return 2 * (size_t)((B + 15) / 16) * (size_t)(lmax + 1) * (size_t)((npairs + 7) / 8) * 512;
 }
 
-hipError_t launch_legendre_fwd_bf16(const Tables &tb, int B, const uint32_t *XE, const uint32_t *XO, void *xt,
-                                    float2 *alm, double f0, double fm, int accum, hipStream_t st,
-                                    const uint32_t *lam) {
-  if (tb.nitems == 0) return hipErrorInvalidValue;
+hipError_t launch_pack_spectra_bf16(const Tables &tb, int B, const uint32_t *XE, const uint32_t *XO, void *xt,
+                                    hipStream_t st) {
   const int M = tb.lmax + 1, Rp = tb.npairs, nrb = (Rp + 7) / 8, ng = (B + 15) / 16;
   if (2 * ng > 65535 || nrb > 65535) return hipErrorInvalidValue;
-  u32x4_t *XT = static_cast<u32x4_t *>(xt);
-  hipLaunchKernelGGL(k_pack_spectra_bf16, dim3((M + 7) / 8, nrb, 2 * ng), dim3(256), 0, st, XE, XO, XT, B, M, Rp,
-                     nrb, ng);
+  hipLaunchKernelGGL(k_pack_spectra_bf16, dim3((M + 7) / 8, nrb, 2 * ng), dim3(256), 0, st, XE, XO,
+                     static_cast<u32x4_t *>(xt), B, M, Rp, nrb, ng);
+  return hipGetLastError();
+}
+
+// Legendre step on the packed spectra xt (k_pack_spectra_bf16's output).
+hipError_t launch_legendre_fwd_bf16(const Tables &tb, int B, const void *xt, float2 *alm, double f0, double fm,
+                                    int accum, hipStream_t st, const uint32_t *lam) {
+  if (tb.nitems == 0) return hipErrorInvalidValue;
+  const int M = tb.lmax + 1, Rp = tb.npairs, nrb = (Rp + 7) / 8, ng = (B + 15) / 16;
+  if (ng > 65535) return hipErrorInvalidValue;
+  const u32x4_t *XT = static_cast<const u32x4_t *>(xt);
   const size_t xt_par = (size_t)ng * M * nrb * 32;
   const dim3 grid(8 * longest_xcd_items(tb.lmax), ng);
   if (lam) {
