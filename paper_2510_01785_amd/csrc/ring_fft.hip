@@ -809,7 +809,7 @@ template <typename T> __device__ __forceinline__ void weigh4(const double *pw, i
 }
 
 template <typename TIn, typename T, typename TS, bool NEST, int NT>
-__global__ void __launch_bounds__(NT, sizeof(T) == 4 ? 4 : 1)
+__global__ void __launch_bounds__(NT, sizeof(T) == 4 ? 4 : 2)
     k_ring_fft_fwd(Tables tb, int B, int G, int tq_off, int bs_nb, const TIn *__restrict__ map,
                    const double *__restrict__ wtab, double wscale, const double *__restrict__ pixw,
                    TS *__restrict__ XE, TS *__restrict__ XO) {
@@ -929,7 +929,7 @@ constexpr int kFoldUnroll = 2;  // (k, channel) items per thread with loads in f
 
 
 template <typename TOut, typename T, int NT>
-__global__ void __launch_bounds__(NT, sizeof(T) == 4 ? 4 : 1)
+__global__ void __launch_bounds__(NT, sizeof(T) == 4 ? 4 : 2)
     k_ring_fft_inv(Tables tb, int B, int G, int tq_off, int bs_nb, const cplx<T> *__restrict__ GN,
                    const cplx<T> *__restrict__ GS, const TOut *__restrict__ sub, TOut *__restrict__ map) {
   using C = cplx<T>;
@@ -1173,10 +1173,10 @@ __global__ void __launch_bounds__(NT, sizeof(T) == 4 ? 4 : 1)
 // lengths up to 4 * 2048; Bluestein rings use convolution lengths M < 2 nside.
 constexpr size_t kMaxLds = 160 * 1024;  // LDS of one gfx950 workgroup
 
-FftGeom fft_geometry(int nside, int mmax_bs, int batch, size_t csize) {
+static FftGeom fft_geometry_nt(int nside, int mmax_bs, int batch, size_t csize, int NT, size_t lds_limit) {
   FftGeom g{};
   const int nmax = 4 * nside;
-  g.NT = kFftThreads;
+  g.NT = NT;
   const int cap = g.NT * kFftOutMax;  // complex values one stage can hold
   int G = cap / nmax;
   const int lds_cap = (int)((72 * 1024) / (nmax * csize));
@@ -1200,12 +1200,29 @@ FftGeom fft_geometry(int nside, int mmax_bs, int batch, size_t csize) {
       const size_t ylds = nb == 4 ? 0 : nb == 2 ? 2 : ylds1;
       bs = ylds * (size_t)(nside - 1) + nb * cs;
       g.bs_nb = nb;
-      if ((size_t)nb * mmax_bs <= (size_t)cap && ((bs > need ? bs : need) + tqn) * csize <= kMaxLds) break;
+      if ((size_t)nb * mmax_bs <= (size_t)cap && ((bs > need ? bs : need) + tqn) * csize <= lds_limit) break;
     }
     if (bs > need) need = bs;
   }
   g.tq_off = (int)need;
   g.lds = (need + tqn) * csize;
+  return g;
+}
+
+// FP64 transforms of 4 or more channels whose channel slice and Bluestein
+// sub-transforms fit a 256-thread stage run 256-thread workgroups with at
+// most half the LDS, two per CU (a 512-thread FP64 workgroup holds one
+// channel of the longest ring in half its threads and, with the Bluestein
+// buffers, most of the LDS: one workgroup per CU).  Measured at Nside 1024,
+// B 16: forward 2.65 -> 2.50 ms, inverse 3.42 -> 2.91 ms; at one channel the
+// Bluestein rings' sub-transforms one at a time made the inverse 8% slower,
+// so smaller batches keep 512 threads.
+FftGeom fft_geometry(int nside, int mmax_bs, int batch, size_t csize) {
+  const FftGeom g = fft_geometry_nt(nside, mmax_bs, batch, csize, kFftThreads, kMaxLds);
+  if (csize == 16 && batch >= 4 && (size_t)g.G * 4 * nside <= 256 * kFftOutMax && mmax_bs <= 256 * kFftOutMax) {
+    const FftGeom h = fft_geometry_nt(nside, mmax_bs, batch, csize, 256, kMaxLds / 2);
+    if (h.lds <= kMaxLds / 2 && h.G == g.G) return h;
+  }
   return g;
 }
 
@@ -1231,10 +1248,13 @@ hipError_t launch_ring_fft_fwd(Tables tb, int B, const TIn *map, const double *w
   const FftGeom g = fft_geometry(tb.nside, tb.mmax_bs, B, sizeof(cplx<T>));
   if (g.lds > kMaxLds) return hipErrorInvalidValue;
   auto kern = nested ? k_ring_fft_fwd<TIn, T, TS, true, kFftThreads> : k_ring_fft_fwd<TIn, T, TS, false, kFftThreads>;
+  if constexpr (sizeof(T) == 8) {
+    if (g.NT == 256) kern = nested ? k_ring_fft_fwd<TIn, T, TS, true, 256> : k_ring_fft_fwd<TIn, T, TS, false, 256>;
+  }
   hipError_t e = allow_lds(kern, g.lds);
   if (e != hipSuccess) return e;
   const unsigned grid = nested ? fft_grid_banded(tb.npairs, B, g.G) : fft_grid(tb.npairs, B, g.G);
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(kFftThreads), g.lds, st, tb, B, g.G, g.tq_off, g.bs_nb, map, wtab, wscale,
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(g.NT), g.lds, st, tb, B, g.G, g.tq_off, g.bs_nb, map, wtab, wscale,
                      pixw, XE, XO);
   return hipGetLastError();
 }
@@ -1245,9 +1265,12 @@ hipError_t launch_ring_fft_inv(Tables tb, int B, const cplx<T> *GN, const cplx<T
   const FftGeom g = fft_geometry(tb.nside, tb.mmax_bs, B, sizeof(cplx<T>));
   if (g.lds > kMaxLds) return hipErrorInvalidValue;
   auto kern = k_ring_fft_inv<TOut, T, kFftThreads>;
+  if constexpr (sizeof(T) == 8) {
+    if (g.NT == 256) kern = k_ring_fft_inv<TOut, T, 256>;
+  }
   hipError_t e = allow_lds(kern, g.lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(kern, dim3(fft_grid(tb.npairs, B, g.G)), dim3(kFftThreads), g.lds, st, tb, B, g.G, g.tq_off,
+  hipLaunchKernelGGL(kern, dim3(fft_grid(tb.npairs, B, g.G)), dim3(g.NT), g.lds, st, tb, B, g.G, g.tq_off,
                      g.bs_nb, GN, GS, sub, map);
   return hipGetLastError();
 }
