@@ -43,10 +43,17 @@ __global__ void __launch_bounds__(kLayoutThreads)
       }
     }
     __syncthreads();
-    for (int q = t; q < ni * nb; q += kLayoutThreads) {
-      const int r = q / nb, b = q - r * nb;
-      const ChanGroup gr = chan_group(b0 + b, B, gmax);
-      ALMT[(size_t)gr.g0 * (nalm + kCoefPad) + (i0 + r) * gr.w + (b0 + b - gr.g0)] = tile[r][b];
+    if (gmax == B && nb == 16) {
+      // one group of all channels, a full slice of 16: row i0 + r of the
+      // [idx][B] layout gets channels b0 .. b0 + 15 (shifts, no division)
+      C *dst = ALMT + i0 * (size_t)B + b0;
+      for (int q = t; q < ni * 16; q += kLayoutThreads) dst[(size_t)(q >> 4) * B + (q & 15)] = tile[q >> 4][q & 15];
+    } else {
+      for (int q = t; q < ni * nb; q += kLayoutThreads) {
+        const int r = q / nb, b = q - r * nb;
+        const ChanGroup gr = chan_group(b0 + b, B, gmax);
+        ALMT[(size_t)gr.g0 * (nalm + kCoefPad) + (i0 + r) * gr.w + (b0 + b - gr.g0)] = tile[r][b];
+      }
     }
     __syncthreads();
   }
