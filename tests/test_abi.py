@@ -32,6 +32,17 @@ def test_status_strings():
     assert L.shtx_version() >= 100
 
 
+def test_stage_names_match_the_binding():
+    """The profiler's stage indices (an ABI of their own: shtx_profile_read
+    takes them) name the stages the binding reads, in its order; indices
+    past the last are rejected."""
+    L = _lib.lib()
+    assert tuple(L.shtx_stage_name(i).decode() for i in range(len(_lib.STAGES))) == _lib.STAGES
+    assert L.shtx_stage_name(len(_lib.STAGES)) == b"unknown"
+    ms, n = ctypes.c_double(), ctypes.c_longlong()
+    assert L.shtx_profile_read(len(_lib.STAGES), ctypes.byref(ms), ctypes.byref(n)) == _lib.ERR_ARG
+
+
 def nalm(l):
     return (l + 1) * (l + 2) // 2
 
