@@ -1,7 +1,8 @@
 """GPU parity at full workload sizes, in the launch configuration the
 benchmark times, against the FP64 oracle on every output element:
 
-  Nside 1024, lmax 2047, 16 FP32 channels (and the same with BF16 maps)
+  Nside 1024, lmax 2047, 16 FP32 channels (and the same with BF16 maps and
+  in FP64)
   Nside 2048, lmax 4095, one channel, FP64 and FP32
   refined analysis (Eq. (4), 3 iterations) at Nside 512, lmax 1023
 
@@ -67,6 +68,28 @@ def test_map2alm_fullsize_nside1024_b16(shtx):
     print("[fullsize] map2alm nside 1024 B 16 f32 rel l2 %.3e" % err, flush=True)
     assert err <= TOL[torch.float32]
     assert np.all(got[:, :lmax + 1].imag == 0)
+
+
+@pytest.mark.parametrize("direction", ["map2alm", "alm2map"])
+def test_fullsize_nside1024_b16_f64(shtx, direction):
+    """The FP64 path at the FP64 benchmark's size: FP64 matrix-core Legendre
+    kernels (two 8-channel analysis groups, one 16-channel synthesis group)
+    and 256-thread FP64 ring FFTs, on the FP32 cases' inputs (values
+    representable in FP32, so the same cached oracle results serve), every
+    output element at the FP64 bar."""
+    nside, lmax, B = 1024, 2047, 16
+    announce("%s full size nside=%d lmax=%d B=%d f64 (every element)" % (direction, nside, lmax, B))
+    if direction == "map2alm":
+        f = f32_map(8100 + nside, B, nside)
+        ref = oracle_map2alm(f, lmax, nside)
+        got = shtx.map2alm(torch.tensor(f, dtype=torch.float64, device="cuda"), lmax).cpu().numpy()
+    else:
+        a = c64_alm(8200 + nside, B, lmax)
+        ref = oracle_alm2map(a, nside, lmax)
+        got = shtx.alm2map(torch.tensor(a, dtype=torch.complex128, device="cuda"), nside, lmax).cpu().numpy()
+    err = rel_l2(got, ref)
+    print("[fullsize] %s nside 1024 B 16 f64 rel l2 %.3e" % (direction, err), flush=True)
+    assert err <= TOL[torch.float64]
 
 
 def test_alm2map_fullsize_nside1024_b16(shtx):
