@@ -18,9 +18,10 @@
 // its four waves take 128-ring slices of every 512-ring chunk, two adjacent
 // rings per lane (two independent FP64 recurrences per lane).  A lane packs
 // its two rings' BF16 lambda of one l into one 32-bit word, so K slot 2q,
-// 2q + 1 of a slice are its rings 2q, 2q + 1.  The spectra of a slice are
-// transposed into that K order through the same LDS tile (B operands kept in
-// registers for the whole block).
+// 2q + 1 of a slice are its rings 2q, 2q + 1.  The spectra arrive in that
+// K order from k_pack_spectra_bf16 (below): one 16-byte load per lane and K
+// step is a B operand, all of a slice issued before the recurrence that
+// precedes their first use and kept in registers for the block.
 //
 // Stored-lambda mode (the paper's precomputed Legendre tensor, Sec. III-G,
 // Eq. (28), kept resident in HBM for a hot (nside, lmax) instead of streamed
