@@ -667,8 +667,8 @@ def run_resize(args):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: the transform is not sharded across GPUs "
-              "(see DESIGN.md for how it would shard); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: the transform is not sharded across GPUs; "
+              "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     import torch
     if args.calibrate_copy_mib:

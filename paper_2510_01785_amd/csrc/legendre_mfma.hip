@@ -24,23 +24,26 @@ __device__ __forceinline__ f32x16 mfma32(float a, float b, f32x16 c) {
 // Word 3 of a raw buffer resource on gfx9-family GPUs (untyped 32-bit
 // loads, no swizzle).
 constexpr int kBufferWord3 = 0x00020000;
-constexpr int kFwdWaves = 4;
 constexpr int kSubL = 64;       // l's per LDS sub-tile (two per block)
 constexpr int kTileRS = 64 + 4; // row stride of the LDS tile in floats
 constexpr int kRedRS = 32 + 1;  // row stride of the cross-wave reduction (reuses the tile)
-static_assert(kFwdWaves * kBlockL * kRedRS <= kFwdWaves * kSubL * kTileRS, "reduction fits the tile");
+static_assert(kBlockL * kRedRS <= kSubL * kTileRS, "reduction fits the tile");
 
 // Analysis.  Workgroup = one (m, l0) item of the XCD-grouped block list;
-// 4 waves take 64-ring slices of every 256-ring chunk; each lane restarts its
+// NW waves take 64-ring slices of every 64 NW-ring chunk; each lane restarts its
 // ring's recurrence from the block checkpoint, writes 64 lambdas per sub-tile
 // into its wave's LDS tile [l][ring], and the wave multiplies the tile (rows =
-// even or odd l) with the ring spectra E or O held in registers.  The four
-// waves' partial sums are added through LDS at the end.
-__global__ void __launch_bounds__(256)
+// even or odd l) with the ring spectra E or O held in registers.  The NW
+// waves' partial sums are added through LDS at the end.  NW = 1 or 2 (launch
+// choice): smaller workgroups than four waves measured faster at every size
+// (more of them, a shorter cross-wave reduction and barriers over fewer
+// waves).
+template <int NW>
+__global__ void __launch_bounds__(64 * NW)
     k_legendre_fwd_mfma(Tables tb, int B, const double *__restrict__ coefA, const float2 *__restrict__ XE,
                         const float2 *__restrict__ XO, float2 *__restrict__ alm, float f0, float fm, int accum) {
   const int b0 = 16 * blockIdx.y;  // channel group of this row of the grid
-  __shared__ float tile[kFwdWaves * kSubL * kTileRS];
+  __shared__ float tile[NW * kSubL * kTileRS];
   __shared__ double sA[kBlockL];
   const int g = blockIdx.x;
   const int x = g & 7, k = g >> 3;
@@ -59,7 +62,7 @@ __global__ void __launch_bounds__(256)
   const bool fast_rows = rowf * 32 * sizeof(float) < (size_t)0x7fffffff;
   {
     const double *Ag = coefA + alm_idx(m, m, L) - m;
-    if (tid < kBlockL) sA[tid] = Ag[min(l0 + tid, L)];
+    for (int t = tid; t < kBlockL; t += 64 * NW) sA[t] = Ag[min(l0 + t, L)];
   }
   __syncthreads();
   float *tw = tile + w * kSubL * kTileRS;
@@ -72,7 +75,7 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc[a][r] = 0.f;
 
-  // this lane's ring per 256-ring chunk: recurrence start (kBlockL: not
+  // this lane's ring per chunk: recurrence start (kBlockL: not
   // active in this block), checkpoint and z, fetched one chunk ahead
   auto fetch_ring = [&](int q, int &t0, double2 &v, double &z) {
     const bool qok = q < Rp;
@@ -84,14 +87,14 @@ __global__ void __launch_bounds__(256)
   double2 vn;
   double zn;
   fetch_ring(w * 64 + j, t0n, vn, zn);
-  for (int c0 = 0; c0 < Rp; c0 += 64 * kFwdWaves) {
+  for (int c0 = 0; c0 < Rp; c0 += 64 * NW) {
     const int t0 = t0n;
     const double2 v = vn;
     const double z = zn;
     // wait for this chunk's values here: the recurrence below then waits for
     // no load, while the spectrum loads issued before it are in flight
     asm volatile("" ::"v"(t0), "v"(v.x), "v"(v.y), "v"(z));
-    fetch_ring(c0 + 64 * kFwdWaves + w * 64 + j, t0n, vn, zn);
+    fetch_ring(c0 + 64 * NW + w * 64 + j, t0n, vn, zn);
     if (__all(t0 >= kBlockL)) continue;  // no ring of this slice is active here
     // last start offset of the wave: later groups need no injection selects;
     // first start offset: a half block before it holds only zero lambdas
@@ -230,13 +233,13 @@ __global__ void __launch_bounds__(256)
   const size_t nalm = nalm_of(L);
   const size_t base = alm_idx(l0, m, L);
   const float f = (m == 0) ? f0 : fm;
-  for (int e = tid; e < 16 * kBlockL; e += 256) {
+  for (int e = tid; e < 16 * kBlockL; e += 64 * NW) {
     const int c = e / kBlockL, lrel = e % kBlockL;  // a wave walks 64 consecutive l of one channel
     const int l = l0 + lrel;
     if (l > L || b0 + c >= B) continue;
     float re = 0.f, im = 0.f;
 #pragma unroll
-    for (int ww = 0; ww < kFwdWaves; ++ww) {
+    for (int ww = 0; ww < NW; ++ww) {
       re += red[(ww * kBlockL + lrel) * kRedRS + 2 * c];
       im += red[(ww * kBlockL + lrel) * kRedRS + 2 * c + 1];
     }
@@ -453,9 +456,17 @@ hipError_t launch_legendre_fwd_mfma(const Tables &tb, int B, const float2 *XE, c
       longest = c > longest ? c : longest;
     }
   }
-  // all 16-channel groups in one launch (one tail instead of one per group)
-  hipLaunchKernelGGL(k_legendre_fwd_mfma, dim3(8 * longest, (B + 15) / 16), dim3(256), 0, st, tb, B, tb.coefA, XE,
-                     XO, alm, (float)f0, (float)fm, accum);
+  // all 16-channel groups in one launch (one tail instead of one per group);
+  // one wave per workgroup from 2048 ring pairs (Nside 1024 B 16: 2.30 ms
+  // against 2.33 with two waves and 2.43 with four), two below (Nside 512
+  // B 16: 0.401 ms against 0.414 with one and 0.411 with four)
+  const dim3 grid(8 * longest, (B + 15) / 16);
+  if (tb.npairs >= 2048)
+    hipLaunchKernelGGL(k_legendre_fwd_mfma<1>, grid, dim3(64), 0, st, tb, B, tb.coefA, XE, XO, alm, (float)f0,
+                       (float)fm, accum);
+  else
+    hipLaunchKernelGGL(k_legendre_fwd_mfma<2>, grid, dim3(128), 0, st, tb, B, tb.coefA, XE, XO, alm, (float)f0,
+                       (float)fm, accum);
   return hipGetLastError();
 }
 
