@@ -15,8 +15,9 @@
 //
 // Work split: a workgroup takes one (m, l0) item of the XCD-grouped block
 // list (blocks of kBlockL l restarted from stored recurrence checkpoints);
-// its four waves take 128-ring slices of every 512-ring chunk, two adjacent
-// rings per lane (two independent FP64 recurrences per lane).  A lane packs
+// its kBfWaves waves (one: measured faster than two or four, Nside 1024 B 16
+// 0.81 ms against 0.83 and 0.88) take 128-ring slices of every chunk, two
+// adjacent rings per lane (two independent FP64 recurrences per lane).  A lane packs
 // its two rings' BF16 lambda of one l into one 32-bit word, so K slot 2q,
 // 2q + 1 of a slice are its rings 2q, 2q + 1.  The spectra arrive in that
 // K order from k_pack_spectra_bf16 (below): one 16-byte load per lane and K
@@ -59,7 +60,7 @@ __device__ __forceinline__ float f64_to_f32(double d) {
   return f;
 }
 
-constexpr int kBfWaves = 4;
+constexpr int kBfWaves = 1;
 constexpr int kBfSlice = 128;                  // rings per wave slice
 constexpr int kBfChunk = kBfWaves * kBfSlice;  // rings per chunk
 constexpr int kBfSub = 64;                     // l per lambda tile (half a block)
@@ -74,7 +75,7 @@ constexpr int kLamTileW = kBfSub * 64;  // words of one stored tile (64 l x 64 r
 constexpr int kLamTileBytes = kLamTileW * 4;
 
 template <int MODE>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(64 * kBfWaves)
     k_legendre_fwd_bf16(Tables tb, int B, const double *__restrict__ coefA, const u32x4_t *__restrict__ XT,
                         size_t xt_par, float2 *__restrict__ alm, float f0, float fm, int accum,
                         const uint32_t *__restrict__ lam_off, uint32_t *__restrict__ lam_tiles) {
@@ -93,7 +94,7 @@ __global__ void __launch_bounds__(256)
   const int h = j >> 5, col = j & 31;
   {
     const double *Ag = coefA + alm_idx(m, m, L) - m;
-    if (tid < kBlockL) sA[tid] = Ag[min(l0 + tid, L)];
+    for (int t = tid; t < kBlockL; t += 64 * kBfWaves) sA[t] = Ag[min(l0 + t, L)];
   }
   __syncthreads();
   uint32_t *tw = tile + w * kBfTileW;
@@ -244,7 +245,7 @@ __global__ void __launch_bounds__(256)
     }
   }
   if constexpr (MODE == kLamBuild) return;
-  // sum the four waves' partial tiles, red[w][l - l0][col], and write the
+  // sum the waves' partial tiles, red[w][l - l0][col], and write the
   // caller's layout alm[b][idx(l, m)] = f_m c_lm a (Im = 0 for m = 0), or add
   __syncthreads();
   float *red = reinterpret_cast<float *>(tile);
@@ -263,7 +264,7 @@ __global__ void __launch_bounds__(256)
   const size_t nalm = nalm_of(L);
   const size_t base = alm_idx(l0, m, L);
   const float f = (m == 0) ? f0 : fm;
-  for (int e = tid; e < 16 * kBlockL; e += 256) {
+  for (int e = tid; e < 16 * kBlockL; e += 64 * kBfWaves) {
     const int c = e / kBlockL, lrel = e % kBlockL;
     const int l = l0 + lrel;
     if (l > L || b0 + c >= B) continue;
@@ -348,10 +349,10 @@ hipError_t launch_legendre_fwd_bf16(const Tables &tb, int B, const void *xt, flo
   const dim3 grid(8 * longest_xcd_items(tb.lmax), ng);
   if (lam) {
     const uint32_t *tiles = lam + lam_header_words(tb.nside, tb.nitems);
-    hipLaunchKernelGGL(k_legendre_fwd_bf16<kLamStored>, grid, dim3(256), 0, st, tb, B, tb.coefA, XT, xt_par, alm,
+    hipLaunchKernelGGL(k_legendre_fwd_bf16<kLamStored>, grid, dim3(64 * kBfWaves), 0, st, tb, B, tb.coefA, XT, xt_par, alm,
                        (float)f0, (float)fm, accum, lam, const_cast<uint32_t *>(tiles));
   } else {
-    hipLaunchKernelGGL(k_legendre_fwd_bf16<kLamCompute>, grid, dim3(256), 0, st, tb, B, tb.coefA, XT, xt_par, alm,
+    hipLaunchKernelGGL(k_legendre_fwd_bf16<kLamCompute>, grid, dim3(64 * kBfWaves), 0, st, tb, B, tb.coefA, XT, xt_par, alm,
                        (float)f0, (float)fm, accum, nullptr, nullptr);
   }
   return hipGetLastError();
@@ -389,7 +390,7 @@ std::vector<uint32_t> lam_tile_offsets(int nside, int lmax, int nitems, const ui
 hipError_t launch_lambda_table_build(const Tables &tb, uint32_t *lam, hipStream_t st) {
   if (tb.nitems == 0) return hipErrorInvalidValue;
   const dim3 grid(8 * longest_xcd_items(tb.lmax), 1);
-  hipLaunchKernelGGL(k_legendre_fwd_bf16<kLamBuild>, grid, dim3(256), 0, st, tb, 16, tb.coefA, nullptr, (size_t)0,
+  hipLaunchKernelGGL(k_legendre_fwd_bf16<kLamBuild>, grid, dim3(64 * kBfWaves), 0, st, tb, 16, tb.coefA, nullptr, (size_t)0,
                      nullptr, 1.f, 1.f, 0, lam, lam + lam_header_words(tb.nside, tb.nitems));
   return hipGetLastError();
 }

@@ -213,7 +213,7 @@ __global__ void __launch_bounds__(64 * NW)
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
   }
-  // sum the four waves' partial tiles, red[w][l - l0][col] (row stride
+  // sum the waves' partial tiles, red[w][l - l0][col] (row stride
   // kRedRS: the reads below walk l, conflict-free), and write the caller's
   // layout alm[b][idx(l, m)] = f_m c_lm a (Im = 0 for m = 0), or add to it
   __syncthreads();

@@ -17,14 +17,14 @@
 // broadcast per product.
 //
 // Work split: a workgroup takes one (m, l0) item of the XCD-grouped block
-// list; its four waves take 64-ring slices of every 256-ring chunk, one ring
-// per lane.  Per 32-l sub-tile a lane writes its ring's 32 mu values into
+// list; its NW waves (one or two, by size) take 64-ring slices of every
+// 64 NW-ring chunk, one ring per lane.  Per 32-l sub-tile a lane writes its ring's 32 mu values into
 // its wave's LDS tile (rows: the 16 even l, then the 16 odd l; columns: the
 // 64 rings), and the wave multiplies the two 16-row parity tiles with the
 // slice's spectra E and O, held in registers for the whole block.  K step
 // 2 t + e of lane group q (= lane / 16) is ring 8 t + 2 q + e of the slice,
 // so one 16-byte LDS read gives a lane the A values of two K steps.  The
-// four waves' partial sums are added through LDS at the end.
+// waves' partial sums are added through LDS at the end.
 #include "common.h"
 
 namespace shtx {
@@ -35,22 +35,24 @@ __device__ __forceinline__ f64x4_t mfma64(double a, double b, f64x4_t c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-constexpr int kW64 = 4;         // waves per workgroup
 constexpr int kSub64 = 32;      // l per LDS sub-tile
 constexpr int kRS64 = 64 + 2;   // tile row stride in doubles: 16-byte rows, a
                                 // column read of 16 rows hits 16 distinct bank groups
 constexpr int kRed64 = 16 + 1;  // row stride of the cross-wave reduction (doubles)
-constexpr int kTile64 = kW64 * kSub64 * kRS64;
-constexpr int kRedN64 = kW64 * kBlockL * kRed64;
+// LDS doubles per wave: the lambda tile, or the wave's share of the
+// cross-wave reduction at the end (the larger)
+constexpr int kTile64 = kSub64 * kRS64;
+constexpr int kRedN64 = kBlockL * kRed64;
 constexpr int kLds64 = kTile64 > kRedN64 ? kTile64 : kRedN64;
 static_assert(kBlockL == 4 * kSub64, "four sub-tiles per block");
 
-__global__ void __launch_bounds__(256)
+template <int NW>
+__global__ void __launch_bounds__(64 * NW)
     k_legendre_fwd_mfma64(Tables tb, int B, const double *__restrict__ coefA, const double2 *__restrict__ XE,
                           const double2 *__restrict__ XO, double2 *__restrict__ alm, double f0, double fm,
                           int accum) {
   const int b0 = 8 * blockIdx.y;  // channel group of this row of the grid
-  __shared__ __attribute__((aligned(16))) double lds[kLds64];
+  __shared__ __attribute__((aligned(16))) double lds[NW * kLds64];
   __shared__ double sA[kBlockL];
   const int g = blockIdx.x;
   const int x = g & 7, kx = g >> 3;
@@ -67,7 +69,7 @@ __global__ void __launch_bounds__(256)
   const int cch = min(b0 + (n >> 1), B - 1);
   {
     const double *Ag = coefA + alm_idx(m, m, L) - m;
-    if (tid < kBlockL) sA[tid] = Ag[min(l0 + tid, L)];
+    for (int t = tid; t < kBlockL; t += 64 * NW) sA[t] = Ag[min(l0 + t, L)];
   }
   __syncthreads();
   double *tw = lds + w * kSub64 * kRS64;
@@ -92,12 +94,12 @@ __global__ void __launch_bounds__(256)
   double2 vn;
   double zn;
   fetch_ring(w * 64 + j, t0n, vn, zn);
-  for (int c0 = 0; c0 < Rp; c0 += 64 * kW64) {
+  for (int c0 = 0; c0 < Rp; c0 += 64 * NW) {
     const int t0 = t0n;
     const double2 v = vn;
     const double z = zn;
     asm volatile("" ::"v"(t0), "v"(v.x), "v"(v.y), "v"(z));
-    fetch_ring(c0 + 64 * kW64 + w * 64 + j, t0n, vn, zn);
+    fetch_ring(c0 + 64 * NW + w * 64 + j, t0n, vn, zn);
     if (__all(t0 >= kBlockL)) continue;  // no ring of this slice is active here
     // last start offset of the slice (later groups need no injection
     // selects) and first (sub-tiles before it hold only zero lambdas)
@@ -189,7 +191,7 @@ __global__ void __launch_bounds__(256)
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
   }
-  // sum the four waves' partial tiles, red[w][l - l0][col], and write the
+  // sum the waves' partial tiles, red[w][l - l0][col], and write the
   // caller's layout alm[b][idx(l, m)] = f_m c_lm a (Im = 0 for m = 0), or add
   __syncthreads();
   double *red = lds;
@@ -207,13 +209,13 @@ __global__ void __launch_bounds__(256)
   const size_t nalm = nalm_of(L);
   const size_t base = alm_idx(l0, m, L);
   const double f = (m == 0) ? f0 : fm;
-  for (int e = tid; e < 8 * kBlockL; e += 256) {
+  for (int e = tid; e < 8 * kBlockL; e += 64 * NW) {
     const int c = e / kBlockL, lrel = e % kBlockL;
     const int l = l0 + lrel;
     if (l > L || b0 + c >= B) continue;
     double re = 0.0, im = 0.0;
 #pragma unroll
-    for (int ww = 0; ww < kW64; ++ww) {
+    for (int ww = 0; ww < NW; ++ww) {
       re += red[(ww * kBlockL + lrel) * kRed64 + 2 * c];
       im += red[(ww * kBlockL + lrel) * kRed64 + 2 * c + 1];
     }
@@ -429,8 +431,15 @@ hipError_t launch_legendre_fwd_mfma64(const Tables &tb, int B, const double2 *XE
     for (int m = xg; m <= tb.lmax; m += 8) c += (tb.lmax - m + kBlockL) / kBlockL;
     longest = c > longest ? c : longest;
   }
-  hipLaunchKernelGGL(k_legendre_fwd_mfma64, dim3(8 * longest, (B + 7) / 8), dim3(256), 0, st, tb, B, tb.coefA, XE,
-                     XO, alm, f0, fm, accum);
+  // one wave per workgroup from 2048 ring pairs, two below (as the FP32
+  // analysis; Nside 1024 B 16: 4.82 ms against 4.91 with two waves and 5.01
+  // with four; Nside 512 B 8: 0.390 ms with two, 0.399 with one)
+  const dim3 grid(8 * longest, (B + 7) / 8);
+  if (tb.npairs >= 2048)
+    hipLaunchKernelGGL(k_legendre_fwd_mfma64<1>, grid, dim3(64), 0, st, tb, B, tb.coefA, XE, XO, alm, f0, fm, accum);
+  else
+    hipLaunchKernelGGL(k_legendre_fwd_mfma64<2>, grid, dim3(128), 0, st, tb, B, tb.coefA, XE, XO, alm, f0, fm,
+                       accum);
   return hipGetLastError();
 }
 
