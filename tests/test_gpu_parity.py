@@ -180,7 +180,8 @@ def test_fp32_legendre_paths(shtx, nside, lmax, batch, path, monkeypatch):
 
 
 @pytest.mark.parametrize("nside,lmax,batch,path", [(32, 95, 16, "mfma"), (16, 47, 19, "mfma"), (8, 31, 1, "mfma"),
-                                                   (64, 255, 9, "mfma"),
+                                                   (64, 255, 9, "mfma"), (1, 0, 4, "mfma"), (2, 7, 3, "mfma"),
+                                                   (4, 15, 5, "default"),
                                                    (32, 95, 5, "valu"), (64, 191, 16, "valu"),
                                                    (64, 191, 2, "default"), (64, 191, 3, "default")])
 def test_fp64_legendre_paths(shtx, nside, lmax, batch, path, monkeypatch):
