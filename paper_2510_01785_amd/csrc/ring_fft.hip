@@ -34,6 +34,24 @@ __device__ __forceinline__ int lstride(int s, int pad) { return pad ? s + (s >> 
 inline size_t lds_elems(size_t n) { return n + (n >> 4) + 1; }
 constexpr int kPadMin = 256;  // transform length from which the buffer is padded
 
+// Index quotients floor(x / d) for 0 <= x < 2^20, 1 <= d < 2^24, by a
+// workgroup-uniform d, without the integer division sequence (about twenty
+// instructions per quotient): (x + 1/2) / d lies at least 1/(2d) from every
+// integer, and fma(x, r, r/2) with r the hardware reciprocal of d (1 ulp)
+// is within a relative 2^-22 of it, an absolute error below
+// 2^20 2^-22 / d = 1/(4d), so truncation gives the quotient exactly.  Every
+// quotient of this file has x below 16 channels times 4 * 2048 + 8 samples.
+struct FastDiv {
+  float r, h;
+  int d;
+  __device__ __forceinline__ explicit FastDiv(int dd) : d(dd) {
+    r = __builtin_amdgcn_rcpf((float)dd);
+    h = 0.5f * r;
+  }
+  __device__ __forceinline__ int quo(int x) const { return (int)__builtin_fmaf((float)x, r, h); }
+  __device__ __forceinline__ int rem(int x, int q) const { return x - __mul24(q, d); }
+};
+
 // Lanes per fold item of the inverse: on short rings every k collects many
 // aliases m = +-k mod n (about (lmax + 1) / n per direction), so the aliases
 // of one item are dealt to S consecutive lanes of a wave (S a power of two,
@@ -366,6 +384,7 @@ __device__ __forceinline__ void stage_mix_p2(cplx<T> *buf, int n, int G, int p, 
   const int Tq = n / R;
   const int nb = G * Tq;
   const int step = n / (R * p);
+  const FastDiv dq(Tq);  // p is a power of two here: k = i mod p by a mask
   int tid = threadIdx.x;
   asm volatile("" : "+v"(tid));
   C v[NB][R];
@@ -373,8 +392,8 @@ __device__ __forceinline__ void stage_mix_p2(cplx<T> *buf, int n, int G, int p, 
   for (int s = 0; s < NB; ++s) {
     const int b = tid + s * NT;
     if (b < nb) {
-      const int c = b / Tq, i = b - c * Tq;
-      const int k = i % p;
+      const int c = dq.quo(b), i = dq.rem(b, c);
+      const int k = i & (p - 1);
       const int e = k * step;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
@@ -389,8 +408,8 @@ __device__ __forceinline__ void stage_mix_p2(cplx<T> *buf, int n, int G, int p, 
   for (int s = 0; s < NB; ++s) {
     const int b = tid + s * NT;
     if (b < nb) {
-      const int c = b / Tq, i = b - c * Tq;
-      const int k = i % p;
+      const int c = dq.quo(b), i = dq.rem(b, c);
+      const int k = i & (p - 1);
       const int o0 = (i - k) * R + k;
 #pragma unroll
       for (int q = 0; q < R; ++q) buf[lidx(c * n + o0 + q * p, pad)] = v[s][q];
@@ -412,6 +431,7 @@ __device__ __forceinline__ void stage_odd(cplx<T> *buf, int n, int G, int p, int
   const int Tn = n / R;
   const int pR = p * R;
   const int step = n / pR;
+  const FastDiv dn(n), dpr(pR), dp(p);
   int tid = threadIdx.x;
   asm volatile("" : "+v"(tid));
   C out[kFftOutMax];
@@ -419,12 +439,12 @@ __device__ __forceinline__ void stage_odd(cplx<T> *buf, int n, int G, int p, int
   for (int s = 0; s < kFftOutMax; ++s) {
     const int o = tid + s * NT;
     if (o < tot) {
-      const int c = o / n;
-      const int oo = o - c * n;
-      const int g = oo / pR;
-      const int rr = oo - g * pR;
-      const int q = rr / p;
-      const int k = rr - q * p;
+      const int c = dn.quo(o);
+      const int oo = dn.rem(o, c);
+      const int g = dpr.quo(oo);
+      const int rr = dpr.rem(oo, g);
+      const int q = dp.quo(rr);
+      const int k = dp.rem(rr, q);
       const int xb = c * n + g * p + k;
       const int be = step * (k + q * p);
       C acc = buf[lidx(xb, pad)];
@@ -554,6 +574,8 @@ __device__ __forceinline__ void ring_dft_bs4(const Tables &tb, int p, int M, int
   const Fuse<T> fz = make_fuse<T>(TabOf<T>::chirp(tb) + roots_offset(i), i, TabOf<T>::bhat(tb) + tb.rp_bsoff[p], M,
                                   (T)1 / (T)M);
   const int logM = __builtin_ctz(M);
+  const int lnb = nb >> 1;  // log2 nb for nb = 1, 2, 4
+  const FastDiv di(i);
   // opaque copies of the thread index per phase (as in stage_p2): index
   // arithmetic hoisted out of the pass loop would stay live and spill
   int tid = threadIdx.x;
@@ -564,8 +586,8 @@ __device__ __forceinline__ void ring_dft_bs4(const Tables &tb, int p, int M, int
     asm volatile("" : "+v"(tid));
     if (S == 1) {
       for (int e = tid; e < gc * nb * i; e += NT) {
-        const int cc = e / i, j = e - cc * i;  // convolution channel cc = (channel, sub-transform)
-        wb[cc * cs + lidx(j, padM)] = input(cc / nb, 4 * j + q0 + cc % nb, 0, 1);
+        const int cc = di.quo(e), j = di.rem(e, cc);  // convolution channel cc = (channel, sub-transform)
+        wb[cc * cs + lidx(j, padM)] = input(cc >> lnb, 4 * j + q0 + (cc & (nb - 1)), 0, 1);
       }
     } else {
       // S lanes per sample, each returning its share (a wave-uniform loop:
@@ -575,9 +597,9 @@ __device__ __forceinline__ void ring_dft_bs4(const Tables &tb, int p, int M, int
         const int e = e0 + (tid & 63);
         const bool ok = e < tot;
         const int it = e >> ls, r = e & (S - 1);
-        const int cc = it / i, j = it - cc * i;
+        const int cc = di.quo(it), j = di.rem(it, cc);
         C v = cmk<C>(0, 0);
-        if (ok) v = input(cc / nb, 4 * j + q0 + cc % nb, r, S);
+        if (ok) v = input(cc >> lnb, 4 * j + q0 + (cc & (nb - 1)), r, S);
         v = group_sum(v, S);
         if (ok && r == 0) wb[cc * cs + lidx(j, padM)] = v;
       }
@@ -598,7 +620,7 @@ __device__ __forceinline__ void ring_dft_bs4(const Tables &tb, int p, int M, int
       }
     } else {
       for (int e = tid; e < nb * i; e += NT) {
-        const int c = e / i, s = e - c * i;
+        const int c = di.quo(e), s = di.rem(e, c);
         buf[(q0 + c) * i + s] = wb[c * cs + lidx(s, padM)];
       }
     }
@@ -613,7 +635,7 @@ __device__ __forceinline__ void ring_dft_bs4(const Tables &tb, int p, int M, int
 #pragma unroll
   for (int u = 0; u < NS; ++u) {
     const int e = tid + u * NT;  // (channel, s)
-    const int c = e / i, s = e - c * i;
+    const int c = di.quo(e), s = di.rem(e, c);
     if (c < gc) {
       C y[4];
 #pragma unroll
@@ -633,7 +655,7 @@ __device__ __forceinline__ void ring_dft_bs4(const Tables &tb, int p, int M, int
 #pragma unroll
   for (int u = 0; u < NS; ++u) {
     const int e = tid + u * NT;
-    const int c = e / i, s = e - c * i;
+    const int c = di.quo(e), s = di.rem(e, c);
     if (c < gc) {
       dft4(z[u][0], z[u][1], z[u][2], z[u][3]);
 #pragma unroll
@@ -830,6 +852,7 @@ __global__ void __launch_bounds__(NT, sizeof(T) == 4 ? 4 : 2)
   const int pad = Mbs == 0 && n >= kPadMin;  // Bluestein rings leave their DFT unpadded
   const int Gp = Mbs ? bs_channels<NT>(G, bs_nb, Mbs, n, tq_off) : G;
   const int nq = n >> 2;  // quads of pixels per ring
+  const FastDiv dnq(nq);
   const RingPhase<T> rph = ring_phase<T>(tb, n, num);
   const int tid = threadIdx.x;
 #pragma unroll 1
@@ -859,7 +882,7 @@ __global__ void __launch_bounds__(NT, sizeof(T) == 4 ? 4 : 2)
         for (int u = 0; u < kLoadUnroll; ++u) {
           const int q = q0 + u * NT;
           if (q < gc * nq) {
-            const int c = q / nq, j = 4 * (q - c * nq);
+            const int c = dnq.quo(q), j = 4 * dnq.rem(q, c);
             const TIn *row = map + (size_t)(b0 + c) * npix;
             load_ring4<NEST, T, TIn>(tb, row, sN, j, fN[u]);
             if (!equator) load_ring4<NEST, T, TIn>(tb, row, sS, j, fS[u]);
@@ -873,7 +896,7 @@ __global__ void __launch_bounds__(NT, sizeof(T) == 4 ? 4 : 2)
         for (int u = 0; u < kLoadUnroll; ++u) {
           const int q = q0 + u * NT;
           if (q < gc * nq) {
-            const int c = q / nq, j = 4 * (q - c * nq);
+            const int c = dnq.quo(q), j = 4 * dnq.rem(q, c);
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
               const T a = fN[u][e], b = equator ? (T)0 : fS[u][e];
@@ -888,8 +911,9 @@ __global__ void __launch_bounds__(NT, sizeof(T) == 4 ? 4 : 2)
     // E/O spectra for m = 0..L; one phase per m, channels contiguous
     const size_t obase = (size_t)p * M * B + b0;
     const bool pairs = ((B | b0) & 1) == 0;  // channel pairs start 16-byte aligned
+    const FastDiv d2n(2 * n);
     for (int m = tid; m < M; m += NT) {
-      const int mm = m < 2 * n ? m : m % (2 * n);  // m mod 2n
+      const int mm = m < 2 * n ? m : d2n.rem(m, d2n.quo(m));  // m mod 2n
       const int k = mm < n ? mm : mm - n;          // m mod n
       const int kc = (k == 0) ? 0 : n - k;
       C ph = rph.minus(mm);
@@ -1091,6 +1115,7 @@ __global__ void __launch_bounds__(NT, sizeof(T) == 4 ? 4 : 2)
       // k = 0..n/2; each item also writes k' = n - k (conjugate sums)
       const int nk = gc * ((n >> 1) + 1);
       const int S = fold_lanes(nk, n, M, NT);
+      const FastDiv dgc(gc);
       if (S > 1) {
         // short ring: S lanes per item (a wave-uniform loop: every lane of a
         // wave takes part in the shuffles)
@@ -1100,7 +1125,7 @@ __global__ void __launch_bounds__(NT, sizeof(T) == 4 ? 4 : 2)
           const int e = e0 + (tid & 63);
           const bool ok = e < tot;
           const int j = e >> ls, r = e & (S - 1);
-          const int k = j / gc, c = j - k * gc;
+          const int k = dgc.quo(j), c = dgc.rem(j, k);
           C cn = cmk<C>(0, 0), cs = cmk<C>(0, 0);
           if (ok) fold_part(gn, gs, k, c, r, S, cn, cs);
           cn = group_sum(cn, S);
@@ -1117,14 +1142,14 @@ __global__ void __launch_bounds__(NT, sizeof(T) == 4 ? 4 : 2)
 #pragma unroll
         for (int u = 0; u < kFoldUnroll; ++u) {
           const int j = j0 + u * NT;
-          const int k = j / gc, c = j - k * gc;  // channel fastest: adjacent channels adjacent in memory
+          const int k = dgc.quo(j), c = dgc.rem(j, k);  // channel fastest: adjacent channels adjacent in memory
           if (j < nk) fold_load(gn, gs, k, c, pn[u], ps[u], qn[u], qs[u]);
         }
 #pragma unroll
         for (int u = 0; u < kFoldUnroll; ++u) {
           const int j = j0 + u * NT;
           if (j >= nk) continue;
-          const int k = j / gc, c = j - k * gc;
+          const int k = dgc.quo(j), c = dgc.rem(j, k);
           C cn, cs;
           fold_sums(gn, gs, k, c, pn[u], ps[u], qn[u], qs[u], cn, cs);
           // conj(h) at k and at n - k, h = C_N + i C_S
@@ -1138,8 +1163,9 @@ __global__ void __launch_bounds__(NT, sizeof(T) == 4 ? 4 : 2)
     // IDFT(h) = conj(F): f_N = F.x, f_S = -F.y; four consecutive pixels per
     // item (ring starts and lengths are multiples of 4 pixels)
     const int nq = n >> 2;
+    const FastDiv dnq(nq);
     for (int q = tid; q < gc * nq; q += NT) {
-      const int c = q / nq, jj = 4 * (q - c * nq);
+      const int c = dnq.quo(q), jj = 4 * dnq.rem(q, c);
       const int j = c * n + jj;
       T fn[4], fs[4];
 #pragma unroll
